@@ -1,0 +1,224 @@
+"""Benchmark: sphere<->grid round trips per second on one MI355X.
+
+One step = one round trip over every band of the workload: sphere_to_grid
+(inverse, all bands) followed by grid_to_sphere (forward, all bands), inputs
+resident in HBM. The default workload is the 128^3 grid, |G| <= 32 sphere at
+Gamma (137,065 coefficients), 256 bands, complex128.
+
+Timing follows the paper's protocol (Section 4.1: warm-up iterations, then the
+mean over timed hot iterations). Per-kernel durations come from HIP events
+that the library records around each launch on the execute stream.
+
+Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E peak, GB/s
+WORKLOADS = {
+    # name: (recipe, dtype, flags)
+    "c2": ("c2", "c128", 0),
+    "c3": ("c3", "c64", 0),
+    "c1": ("c1", "c128", 0),
+    "c3alt": ("c3alt", "c64", 0),
+    "c4": ("c4", "c64", 1 | 4),
+    "c4_fp64": ("c4", "c128", 0),
+    "c5": ("c5", "c64", 1 | 4),
+    "c5_fp64": ("c5", "c128", 0),
+}
+DESCR = {
+    "c1": "sphere<->grid 32^3, |G|<=8 (2109 coeffs), Gamma, 4 bands",
+    "c2": "sphere<->grid 128^3, |G|<=32 (137065 coeffs), Gamma, 256 bands",
+    "c3": "sphere<->grid 128^3, |G|<=32 (137065 coeffs), Gamma, 256 bands",
+    "c3alt": "sphere<->grid 32^3, |G|<=8 (2109 coeffs), Gamma, 256 bands",
+    "c4": "sphere<->grid 96^3, 8 k-points, |G+k|<=24, 64 bands each (512 spheres)",
+    "c5": "sphere<->grid 144x160x180, ellipsoid (36,40,45), 4 k-points, 128 bands each",
+}
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "api.cpp", "plan.cpp"):
+        with open(os.path.join(ROOT, "paper_2406_05577_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(workload: str, src_hash: str):
+    """HBM traffic of the plane kernel per launch from the committed rocprofv3
+    counter summary, only if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+        e = d.get(workload)
+        if e and e.get("source_hash") == src_hash:
+            return e.get("plane_bytes_per_launch")
+    except (OSError, ValueError):
+        pass
+    return None
+
+
+def cpu_baseline(w_name: str, sample_bands: int):
+    """The FP64 oracle, as it stands, timed on the host cores on a band sample
+    of the same workload; scaled to round trips of the whole workload."""
+    import numpy as np
+    import oracle
+    import synth
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count() or 1
+    rec = synth.RECIPES[w_name]
+    w = synth.make_workload(w_name, nbands=sample_bands, nkpts=1)
+    s = w.spheres[0]
+    c = w.coeffs[0].astype(np.complex128)
+    t0 = time.perf_counter()
+    g = oracle.sphere_to_grid(w.dims, s.lin, c)
+    oracle.grid_to_sphere(w.dims, s.lin, g)
+    t = time.perf_counter() - t0
+    total_bands = rec["nb"] * max(rec["nk"], 1)
+    rt_per_s = 1.0 / (t * total_bands / sample_bands)
+    return {"value": rt_per_s, "unit": "round_trips/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{sample_bands} of {total_bands} bands (one k-point), one FP64 round trip "
+                      f"in {t:.2f} s, scaled linearly to all bands"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--flags", type=int, default=None, help="override plan flags")
+    ap.add_argument("--tuning", default=None, help="JSON dict of tiling knobs")
+    ap.add_argument("--cpu-sample-bands", type=int, default=48)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true",
+                    help="skip per-kernel event timing (graph replays never record it)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(bands shard across GPUs without any exchange; see the design notes). "
+              "Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2406_05577_amd import Plan
+
+    recipe, dtype, flags = WORKLOADS[args.workload]
+    if args.flags is not None:
+        flags = args.flags
+    tuning = json.loads(args.tuning) if args.tuning else None
+    torch.cuda.set_device(0)
+    w = synth.make_workload(recipe, dtype=dtype)
+    plan = Plan(w.dims, [s.lin for s in w.spheres], [s.nbands for s in w.spheres],
+                kpts=[s.kpt for s in w.spheres], dtype=dtype, flags=flags, tuning=tuning)
+    tdt = torch.complex128 if dtype == "c128" else torch.complex64
+    sph = torch.from_numpy(w.sphere_concat()).to("cuda").to(tdt)
+    back = torch.empty_like(sph)
+    grid = torch.empty(plan.info["grid_elems"], dtype=tdt, device="cuda")
+    es = 16 if dtype == "c128" else 8
+    N = w.ngrid
+    nb_total = w.nbands_total
+    sphere_bytes = plan.info["sphere_elems"] * es
+    grid_bytes = plan.info["grid_elems"] * es
+    b_min = 2 * (grid_bytes + sphere_bytes)       # algorithmic bytes per round trip
+
+    def step():
+        plan.sphere_to_grid(sph, grid)
+        plan.grid_to_sphere(grid, back)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    profile = not args.no_profile and not (flags & 4)
+    plan.set_profiling(profile)
+    plan.get_profile()   # clear
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_total = e0.elapsed_time(e1)
+    prof = plan.get_profile()
+    plan.set_profiling(False)
+    ms = ms_total / args.steps
+    rt_s = 1000.0 / ms
+
+    # round-trip check on the timed output (every band)
+    ref = sph.cpu().numpy()
+    got = back.cpu().numpy()
+    e_rt = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+
+    src_hash = kernel_source_hash()
+    roofline = None
+    kern = {}
+    if profile:
+        for k, (n, t) in prof.items():
+            kern[k] = {"launches": n, "avg_ms": (t / n) if n else None}
+        n_inv, t_inv = prof["plane_inverse"]
+        n_fwd, t_fwd = prof["plane_forward"]
+        if n_inv and n_fwd:
+            avg_s = (t_inv + t_fwd) / (n_inv + n_fwd) / 1000.0
+            ach = grid_bytes / avg_s / 1e9
+            traffic = traffic_from_profiles(args.workload, src_hash)
+            roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                        "traffic": traffic, "kernel": "plane (y then x transforms), both directions",
+                        "algorithmic_bytes_per_launch": grid_bytes,
+                        "avg_launch_ms": round(avg_s * 1000.0, 4)}
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(recipe, min(args.cpu_sample_bands, synth.RECIPES[recipe]["nb"]))
+    out = {
+        "metric": "sphere<->grid 3D FFT round trips/sec and % HBM roofline, FP32 vs FP64",
+        "value": round(rt_s, 3),
+        "unit": "round_trips/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if dtype == "c128" else "f32",
+        "data": "synthetic (seeded complex Gaussian bands on the cutoff sphere)",
+        "config": {"workload": DESCR.get(recipe, recipe), "recipe": recipe,
+                   "complex_dtype": "complex128" if dtype == "c128" else "complex64",
+                   "dims": list(w.dims), "bands": nb_total, "spheres": len(w.spheres),
+                   "coeffs": int(plan.info["total_coeffs"]), "plan_flags": flags,
+                   "tuning": plan.info["tuning"], "radix": {"x": plan.info["radix_x"],
+                   "y": plan.info["radix_y"], "z": plan.info["radix_z"]}},
+        "step_roofline": {"algorithmic_bytes": b_min, "achieved_GBs": round(b_min / (ms / 1000) / 1e9, 1),
+                          "frac": round(b_min / (ms / 1000) / 1e9 / HBM_PEAK_GBS, 4)},
+        "roofline": roofline,
+        "kernels": kern,
+        "band_round_trips_per_s": round(rt_s * nb_total, 1),
+        "round_trip_rel_err": e_rt,
+        "source_hash": src_hash,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,68 @@
+// Kernel argument block shared by the host launcher and the HIP kernels.
+#pragma once
+
+#include <cstdint>
+
+namespace fftb {
+
+constexpr int kAxisStages = 8;
+
+struct AxisDev {
+  int n;
+  int nst;
+  int R[kAxisStages];
+  int p[kAxisStages];
+  int twoff[kAxisStages];
+};
+
+// Per-sphere descriptor (device resident). Offsets are in complex elements
+// (data buffers) or int32 entries (tables).
+struct SphereDesc {
+  int64_t sph_off;     // first S[g][b] of this sphere in the sphere buffer
+  int64_t grid_off;    // first G[z][y][x][b] in the grid buffer
+  int64_t col_off;     // first element of this sphere's column scratch
+  int32_t gidx_off;    // ncol*nz table: coefficient index of (column, z) or -1
+  int32_t colidx_off;  // nslab*ny table: column index of (slab, y) or -1
+  int32_t colmeta_off; // per-column slab index and y
+  int32_t xinv_off;    // nx table: slab index of x or -1
+  int32_t ncol;
+  int32_t nslab;
+  int32_t nb;
+  int32_t nchunk;      // ceil(nb / band_chunk)
+  int32_t k1_start, k1_end;  // task range of the column kernel
+  int32_t k2_start, k2_end;  // task range of the plane kernel
+};
+
+struct KArgs {
+  int nx, ny, nz;
+  int bcl;           // log2(band chunk)
+  int n1, m;         // y residue classes and class length m = ny / n1
+  int lx;            // rows per x batch in the plane kernel
+  int lc;            // columns per column-kernel task
+  int nsph;
+  int k1_tasks, k2_tasks;
+  int persistent;
+  int lds_P, lds_X0, lds_X1;  // element offsets of LDS regions (S starts at 0)
+  AxisDev ax, ay, az;
+  const SphereDesc* sph;
+  const int32_t* gidx;
+  const int32_t* colidx;
+  const int32_t* col_xi;
+  const int32_t* col_y;
+  const int32_t* xinv;
+  const void* twx;      // forward-sign twiddles (double pairs, or FP32 hi)
+  const void* twy;
+  const void* twz;
+  const void* twf;      // exp(-2*pi*i*j/ny), j < ny (fold twiddles)
+  const void* twx_lo;   // FP32 lo parts (null for FP64)
+  const void* twy_lo;
+  const void* twz_lo;
+  const void* twf_lo;
+  const void* in;
+  void* out;
+  void* col;            // column scratch
+  double scale;         // 1/N for the forward direction
+  unsigned int* counters;  // 16 work counters (persistent mode)
+};
+
+}  // namespace fftb

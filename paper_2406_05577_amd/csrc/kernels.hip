@@ -1,0 +1,651 @@
+// HIP kernels for gfx950: the column kernel (z-transforms on the occupied
+// columns) and the plane kernel (y-transforms on the occupied slab, then
+// x-transforms on every row of the plane), both directions, FP64 and FP32.
+//
+// Method (paper, Section 2.2): the sphere is zero-padded one axis at a time and
+// each padding step is fused with the 1D transforms on that axis, so the z pass
+// touches only the columns of the xy-projection (the offset array of Section
+// 3.3), the y pass only the occupied x planes, and only the x pass the full grid.
+// Each 1D transform is a mixed-radix Cooley-Tukey FFT (Section 2.1) executed as
+// Stockham stages with radices 2..16 in registers and LDS exchanges between
+// stages.
+//
+// Data layout: band index fastest everywhere (Section 3.3). A workgroup tile
+// holds a chunk of 2^bcl consecutive bands; lanes map to bands first, so every
+// global access of a wavefront covers contiguous band segments and every LDS
+// access is bank-linear.
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+#include <utility>
+
+#include "kargs.hpp"
+
+namespace fftb {
+
+constexpr int kMaxRadixDev = 16;
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cpx {
+  T re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ cpx<T> cadd(cpx<T> a, cpx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> csub(cpx<T> a, cpx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> cscale(cpx<T> a, T s) { return {a.re * s, a.im * s}; }
+// multiply by S*i
+template <int S, typename T>
+__device__ __forceinline__ cpx<T> mul_si(cpx<T> a) {
+  if constexpr (S > 0) return {-a.im, a.re};
+  else return {a.im, -a.re};
+}
+
+// ---------------------------------------------------------------------------
+// Compile-time roots of unity for the in-register codelets: cos and sin of
+// 2*pi*j/R, reduced exactly in integers to the first octant, then a Taylor
+// series (|x| <= pi/4, 14 terms).
+constexpr double kHalfPi = 1.57079632679489661923132169163975144;
+
+constexpr double taylor_sin(double x) {
+  double x2 = x * x, term = x, sum = x;
+  for (int k = 1; k < 14; ++k) {
+    term *= -x2 / ((2.0 * k) * (2.0 * k + 1.0));
+    sum += term;
+  }
+  return sum;
+}
+constexpr double taylor_cos(double x) {
+  double x2 = x * x, term = 1.0, sum = 1.0;
+  for (int k = 1; k < 14; ++k) {
+    term *= -x2 / ((2.0 * k - 1.0) * (2.0 * k));
+    sum += term;
+  }
+  return sum;
+}
+// first-quadrant angle (pi/2) * r / R, 0 <= r < R
+constexpr double q_sin(int r, int R) {
+  return (2 * r <= R) ? taylor_sin(kHalfPi * r / R) : taylor_cos(kHalfPi * (R - r) / R);
+}
+constexpr double q_cos(int r, int R) {
+  return (2 * r <= R) ? taylor_cos(kHalfPi * r / R) : taylor_sin(kHalfPi * (R - r) / R);
+}
+// cos(2*pi*j/R), sin(2*pi*j/R)
+constexpr double kcos(int j, int R) {
+  j = ((j % R) + R) % R;
+  const int q = (4 * j) / R, r = 4 * j - q * R;
+  const double c = q_cos(r, R), s = q_sin(r, R);
+  return q == 0 ? c : q == 1 ? -s : q == 2 ? -c : s;
+}
+constexpr double ksin(int j, int R) {
+  j = ((j % R) + R) % R;
+  const int q = (4 * j) / R, r = 4 * j - q * R;
+  const double c = q_cos(r, R), s = q_sin(r, R);
+  return q == 0 ? s : q == 1 ? c : q == 2 ? -s : -c;
+}
+
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
+// x * exp(S*2*pi*i*J/R), with exact quarter turns folded at compile time.
+template <int J, int R, int S, typename T>
+__device__ __forceinline__ cpx<T> rot(cpx<T> x) {
+  constexpr int j = ((J % R) + R) % R;
+  if constexpr (j == 0) {
+    return x;
+  } else if constexpr (4 * j == R) {
+    return mul_si<S>(x);
+  } else if constexpr (2 * j == R) {
+    return {-x.re, -x.im};
+  } else if constexpr (4 * j == 3 * R) {
+    return mul_si<-S>(x);
+  } else {
+    constexpr T c = static_cast<T>(kcos(j, R));
+    constexpr T s = static_cast<T>(S * ksin(j, R));
+    return {x.re * c - x.im * s, x.re * s + x.im * c};
+  }
+}
+
+// ---------------------------------------------------------------------------
+// DFT codelets in registers, sign S (+1: exp(+...), -1: exp(-...)).
+template <int R, int S, typename T>
+__device__ __forceinline__ void dft(cpx<T>* v);
+
+template <int S, typename T>
+__device__ __forceinline__ void dft2(cpx<T>* v) {
+  const cpx<T> a = v[0], b = v[1];
+  v[0] = cadd(a, b);
+  v[1] = csub(a, b);
+}
+template <int S, typename T>
+__device__ __forceinline__ void dft3(cpx<T>* v) {
+  constexpr T h = static_cast<T>(0.866025403784438646763723170752936183);  // sin(2pi/3)
+  const cpx<T> a = v[0], b = v[1], c = v[2];
+  const cpx<T> t1 = cadd(b, c);
+  const cpx<T> t2 = {a.re - static_cast<T>(0.5) * t1.re, a.im - static_cast<T>(0.5) * t1.im};
+  const cpx<T> t3 = mul_si<S>(cscale(csub(b, c), h));
+  v[0] = cadd(a, t1);
+  v[1] = cadd(t2, t3);
+  v[2] = csub(t2, t3);
+}
+template <int S, typename T>
+__device__ __forceinline__ void dft4(cpx<T>* v) {
+  const cpx<T> a = v[0], b = v[1], c = v[2], d = v[3];
+  const cpx<T> s0 = cadd(a, c), s1 = csub(a, c), s2 = cadd(b, d);
+  const cpx<T> s3 = mul_si<S>(csub(b, d));
+  v[0] = cadd(s0, s2);
+  v[2] = csub(s0, s2);
+  v[1] = cadd(s1, s3);
+  v[3] = csub(s1, s3);
+}
+template <int S, typename T>
+__device__ __forceinline__ void dft5(cpx<T>* v) {
+  constexpr T c1 = static_cast<T>(kcos(1, 5)), c2 = static_cast<T>(kcos(2, 5));
+  constexpr T s1 = static_cast<T>(ksin(1, 5)), s2 = static_cast<T>(ksin(2, 5));
+  const cpx<T> a0 = v[0];
+  const cpx<T> t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
+  const cpx<T> t3 = csub(v[1], v[4]), t4 = csub(v[2], v[3]);
+  const cpx<T> r1 = {a0.re + c1 * t1.re + c2 * t2.re, a0.im + c1 * t1.im + c2 * t2.im};
+  const cpx<T> r2 = {a0.re + c2 * t1.re + c1 * t2.re, a0.im + c2 * t1.im + c1 * t2.im};
+  const cpx<T> i1 = mul_si<S>(cpx<T>{s1 * t3.re + s2 * t4.re, s1 * t3.im + s2 * t4.im});
+  const cpx<T> i2 = mul_si<S>(cpx<T>{s2 * t3.re - s1 * t4.re, s2 * t3.im - s1 * t4.im});
+  v[0] = cadd(a0, cadd(t1, t2));
+  v[1] = cadd(r1, i1);
+  v[4] = csub(r1, i1);
+  v[2] = cadd(r2, i2);
+  v[3] = csub(r2, i2);
+}
+
+// R = A*B: B sub-DFTs of length A over stride-B elements, twiddles, then A
+// sub-DFTs of length B (Section 2.1, Cooley-Tukey factorisation).
+template <int A, int B, int S, typename T>
+__device__ __forceinline__ void dft_ab(cpx<T>* v) {
+  constexpr int R = A * B;
+  cpx<T> u[R];
+  static_for<0, B>([&](auto bb) {
+    constexpr int b = decltype(bb)::value;
+    cpx<T> t[A];
+#pragma unroll
+    for (int a = 0; a < A; ++a) t[a] = v[b + B * a];
+    dft<A, S>(t);
+    static_for<0, A>([&](auto aa) {
+      constexpr int ap = decltype(aa)::value;
+      u[b * A + ap] = rot<b * ap, R, S>(t[ap]);
+    });
+  });
+#pragma unroll
+  for (int ap = 0; ap < A; ++ap) {
+    cpx<T> t[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) t[b] = u[b * A + ap];
+    dft<B, S>(t);
+#pragma unroll
+    for (int bp = 0; bp < B; ++bp) v[ap + A * bp] = t[bp];
+  }
+}
+
+template <int R, int S, typename T>
+__device__ __forceinline__ void dft(cpx<T>* v) {
+  if constexpr (R == 1) {
+  } else if constexpr (R == 2) {
+    dft2<S>(v);
+  } else if constexpr (R == 3) {
+    dft3<S>(v);
+  } else if constexpr (R == 4) {
+    dft4<S>(v);
+  } else if constexpr (R == 5) {
+    dft5<S>(v);
+  } else if constexpr (R == 6) {
+    dft_ab<3, 2, S>(v);
+  } else if constexpr (R == 8) {
+    dft_ab<4, 2, S>(v);
+  } else if constexpr (R == 9) {
+    dft_ab<3, 3, S>(v);
+  } else if constexpr (R == 10) {
+    dft_ab<5, 2, S>(v);
+  } else if constexpr (R == 12) {
+    dft_ab<4, 3, S>(v);
+  } else if constexpr (R == 15) {
+    dft_ab<5, 3, S>(v);
+  } else if constexpr (R == 16) {
+    dft_ab<4, 4, S>(v);
+  } else {
+    static_assert(R == 1, "unsupported radix");
+  }
+}
+
+template <int S, typename T>
+__device__ __forceinline__ void butterfly(int R, cpx<T>* v) {
+  switch (R) {
+    case 2: dft<2, S>(v); break;
+    case 3: dft<3, S>(v); break;
+    case 4: dft<4, S>(v); break;
+    case 5: dft<5, S>(v); break;
+    case 6: dft<6, S>(v); break;
+    case 8: dft<8, S>(v); break;
+    case 9: dft<9, S>(v); break;
+    case 10: dft<10, S>(v); break;
+    case 12: dft<12, S>(v); break;
+    case 15: dft<15, S>(v); break;
+    case 16: dft<16, S>(v); break;
+    default: break;
+  }
+}
+
+// Twiddle multiply with a forward-sign table entry; S > 0 conjugates it.
+// FP32 applies the compensated pair x*hi + x*lo.
+template <int S, typename T>
+__device__ __forceinline__ cpx<T> twmul(cpx<T> v, const cpx<T>* __restrict__ hi,
+                                         const cpx<T>* __restrict__ lo, int idx) {
+  cpx<T> w = hi[idx];
+  if constexpr (S > 0) w.im = -w.im;
+  if constexpr (std::is_same<T, float>::value) {
+    cpx<T> l = lo[idx];
+    if constexpr (S > 0) l.im = -l.im;
+    const cpx<T> a = cmul(v, w), b = cmul(v, l);
+    return cadd(a, b);
+  } else {
+    (void)lo;
+    return cmul(v, w);
+  }
+}
+
+// One Stockham stage over `nlines` lines of length n (radix R, sub-transform
+// length p): item (line, i, band) reads x[i + q*n/R], twiddles by
+// w_{pR}^{q*(i mod p)}, applies DFT_R and writes y[(i - i mod p)*R + i mod p + q*p].
+template <int S, typename T, class Src, class Dst>
+__device__ __forceinline__ void stage_run(int nlines, int n, int R, int p, const cpx<T>* tw,
+                                          const cpx<T>* twlo, int bcl, Src src, Dst dst) {
+  const int nq = n / R;
+  const int bmask = (1 << bcl) - 1;
+  const int total = (nlines * nq) << bcl;
+  for (int it = threadIdx.x; it < total; it += blockDim.x) {
+    const int bl = it & bmask;
+    const int rest = it >> bcl;
+    const int line = rest / nq;
+    const int i = rest - line * nq;
+    const int k = i % p;
+    cpx<T> v[kMaxRadixDev];
+#pragma unroll
+    for (int q = 0; q < kMaxRadixDev; ++q)
+      if (q < R) v[q] = src(line, i + q * nq, bl);
+    if (p > 1) {
+#pragma unroll
+      for (int q = 1; q < kMaxRadixDev; ++q)
+        if (q < R) v[q] = twmul<S>(v[q], tw, twlo, k * R + q);
+    }
+    butterfly<S>(R, v);
+    const int j = (i - k) * R + k;
+#pragma unroll
+    for (int q = 0; q < kMaxRadixDev; ++q)
+      if (q < R) dst(line, j + q * p, bl, v[q]);
+  }
+}
+
+template <typename T>
+struct LdsSrc {
+  const cpx<T>* buf;
+  int n, bcl;
+  __device__ __forceinline__ cpx<T> operator()(int line, int pos, int bl) const {
+    return buf[((line * n + pos) << bcl) + bl];
+  }
+};
+template <typename T>
+struct LdsDst {
+  cpx<T>* buf;
+  int n, bcl;
+  __device__ __forceinline__ void operator()(int line, int pos, int bl, cpx<T> v) const {
+    buf[((line * n + pos) << bcl) + bl] = v;
+  }
+};
+
+// Run every stage of an axis plan: the first stage reads through `gsrc`, the
+// last writes through `gdst`, intermediate results ping-pong between LDS
+// buffers b0 and b1 (each nlines*n*2^bcl elements).
+template <int S, typename T, class GSrc, class GDst>
+__device__ __forceinline__ void axis_run(const AxisDev& ap, int nlines, const cpx<T>* tw,
+                                         const cpx<T>* twlo, int bcl, cpx<T>* b0, cpx<T>* b1,
+                                         GSrc gsrc, GDst gdst) {
+  const int n = ap.n, nst = ap.nst;
+  if (nst == 1) {
+    stage_run<S, T>(nlines, n, ap.R[0], ap.p[0], tw + ap.twoff[0], twlo ? twlo + ap.twoff[0] : twlo,
+                    bcl, gsrc, gdst);
+    return;
+  }
+  stage_run<S, T>(nlines, n, ap.R[0], ap.p[0], tw + ap.twoff[0], twlo ? twlo + ap.twoff[0] : twlo,
+                  bcl, gsrc, LdsDst<T>{b0, n, bcl});
+  __syncthreads();
+  for (int s = 1; s < nst - 1; ++s) {
+    cpx<T>* from = (s & 1) ? b0 : b1;
+    cpx<T>* to = (s & 1) ? b1 : b0;
+    stage_run<S, T>(nlines, n, ap.R[s], ap.p[s], tw + ap.twoff[s], twlo ? twlo + ap.twoff[s] : twlo,
+                    bcl, LdsSrc<T>{from, n, bcl}, LdsDst<T>{to, n, bcl});
+    __syncthreads();
+  }
+  const int s = nst - 1;
+  const cpx<T>* from = (s & 1) ? b0 : b1;
+  stage_run<S, T>(nlines, n, ap.R[s], ap.p[s], tw + ap.twoff[s], twlo ? twlo + ap.twoff[s] : twlo,
+                  bcl, LdsSrc<T>{from, n, bcl}, gdst);
+}
+
+// ---------------------------------------------------------------------------
+// Task scheduling. Non-persistent: block b takes task (b mod 8)*per + b/8, so
+// the blocks that the hardware places on one XCD walk a contiguous task range
+// (same plane, neighbouring band chunks). Persistent: blocks b with the same
+// b mod 8 drain one queue of that range through an atomic counter.
+__device__ __forceinline__ int static_task(int total) {
+  const int per = (total + 7) >> 3;
+  const int t = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  return t < total ? t : -1;
+}
+__device__ __forceinline__ int dynamic_task(unsigned int* counters, int total) {
+  const int per = (total + 7) >> 3;
+  const int q = blockIdx.x & 7;
+  const unsigned int idx = atomicAdd(&counters[q], 1u);
+  const long t = static_cast<long>(q) * per + idx;
+  return (static_cast<int>(idx) < per && t < total) ? static_cast<int>(t) : -1;
+}
+
+__device__ __forceinline__ int find_sphere_k1(const KArgs& a, int t) {
+  int s = 0;
+  while (s + 1 < a.nsph && t >= a.sph[s].k1_end) ++s;
+  return s;
+}
+__device__ __forceinline__ int find_sphere_k2(const KArgs& a, int t) {
+  int s = 0;
+  while (s + 1 < a.nsph && t >= a.sph[s].k2_end) ++s;
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// Column kernel task: LC columns x one band chunk, z-transform of length nz.
+// S > 0: sphere -> (pad z) -> z-IFFT -> column scratch.
+// S < 0: column scratch -> z-FFT -> gather the sphere's z values, scale 1/N.
+template <int S, typename T>
+__device__ void k1_task(const KArgs& a, int t, cpx<T>* lds) {
+  const int s = find_sphere_k1(a, t);
+  const SphereDesc d = a.sph[s];
+  const int lt = t - d.k1_start;
+  const int ncb = (d.ncol + a.lc - 1) / a.lc;
+  const int cb = lt % ncb, chunk = lt / ncb;
+  const int c0 = cb * a.lc;
+  const int nl = min(a.lc, d.ncol - c0);
+  const int bcl = a.bcl, bc = 1 << bcl;
+  const int b0 = chunk << bcl;
+  const int nz = a.nz, nb = d.nb, ncol = d.ncol;
+  const int32_t* __restrict__ gidx = a.gidx + d.gidx_off;
+  cpx<T>* colbuf = reinterpret_cast<cpx<T>*>(a.col) + d.col_off;
+  const cpx<T>* tw = reinterpret_cast<const cpx<T>*>(a.twz);
+  const cpx<T>* twlo = reinterpret_cast<const cpx<T>*>(a.twz_lo);
+  cpx<T>* b_0 = lds;
+  cpx<T>* b_1 = lds + ((a.lc * nz) << bcl);
+  const int64_t colbase = static_cast<int64_t>(chunk) * nz * ncol;
+  if constexpr (S > 0) {
+    const cpx<T>* __restrict__ in = reinterpret_cast<const cpx<T>*>(a.in) + d.sph_off;
+    auto gsrc = [=](int line, int z, int bl) -> cpx<T> {
+      const int g = gidx[(c0 + line) * nz + z];
+      const int b = b0 + bl;
+      if (g >= 0 && b < nb) return in[static_cast<int64_t>(g) * nb + b];
+      return cpx<T>{0, 0};
+    };
+    auto gdst = [=](int line, int z, int bl, cpx<T> v) {
+      colbuf[((colbase + static_cast<int64_t>(z) * ncol + c0 + line) << bcl) + bl] = v;
+    };
+    axis_run<S, T>(a.az, nl, tw, twlo, bcl, b_0, b_1, gsrc, gdst);
+  } else {
+    cpx<T>* __restrict__ out = reinterpret_cast<cpx<T>*>(a.out) + d.sph_off;
+    const T sc = static_cast<T>(a.scale);
+    auto gsrc = [=](int line, int z, int bl) -> cpx<T> {
+      return colbuf[((colbase + static_cast<int64_t>(z) * ncol + c0 + line) << bcl) + bl];
+    };
+    auto gdst = [=](int line, int z, int bl, cpx<T> v) {
+      const int g = gidx[(c0 + line) * nz + z];
+      const int b = b0 + bl;
+      if (g >= 0 && b < nb) out[static_cast<int64_t>(g) * nb + b] = cscale(v, sc);
+    };
+    axis_run<S, T>(a.az, nl, tw, twlo, bcl, b_0, b_1, gsrc, gdst);
+  }
+  (void)bc;
+}
+
+// Plane kernel task: one z-plane x one band chunk, looping over the n1 residue
+// classes r of the y output index (y = r + n1*k2, k2 < m).
+//  S > 0: fold the plane's columns into the class (S[xi][j2] = sum_t
+//         col(xi, j2 + m*t) * w_ny^{+(j2+m*t)*r}), y-IFFT of length m on every
+//         occupied x, then x-IFFT of every row of the class -> grid.
+//  S < 0: x-FFT of the class's rows keeping the occupied x, y-FFT of length m,
+//         then col(xi, y) += w_ny^{-y*r} * Y[xi][y mod m].
+template <int S, typename T>
+__device__ void k2_task(const KArgs& a, int t, cpx<T>* lds) {
+  const int s = find_sphere_k2(a, t);
+  const SphereDesc d = a.sph[s];
+  const int lt = t - d.k2_start;
+  const int chunk = lt % d.nchunk, z = lt / d.nchunk;
+  const int bcl = a.bcl;
+  const int bmask = (1 << bcl) - 1;
+  const int b0 = chunk << bcl;
+  const int nx = a.nx, ny = a.ny, n1 = a.n1, m = a.m;
+  const int nb = d.nb, ncol = d.ncol, nslab = d.nslab;
+  const int32_t* __restrict__ colidx = a.colidx + d.colidx_off;
+  const int32_t* __restrict__ xinv = a.xinv + d.xinv_off;
+  const int32_t* __restrict__ cxi = a.col_xi + d.colmeta_off;
+  const int32_t* __restrict__ cy = a.col_y + d.colmeta_off;
+  cpx<T>* colp = reinterpret_cast<cpx<T>*>(a.col) + d.col_off +
+                 ((static_cast<int64_t>(chunk) * a.nz + z) * ncol << bcl);
+  const cpx<T>* twx = reinterpret_cast<const cpx<T>*>(a.twx);
+  const cpx<T>* twxl = reinterpret_cast<const cpx<T>*>(a.twx_lo);
+  const cpx<T>* twy = reinterpret_cast<const cpx<T>*>(a.twy);
+  const cpx<T>* twyl = reinterpret_cast<const cpx<T>*>(a.twy_lo);
+  const cpx<T>* twf = reinterpret_cast<const cpx<T>*>(a.twf);
+  const cpx<T>* twfl = reinterpret_cast<const cpx<T>*>(a.twf_lo);
+  cpx<T>* Sb = lds;
+  cpx<T>* Pb = lds + a.lds_P;
+  cpx<T>* X0 = lds + a.lds_X0;
+  cpx<T>* X1 = lds + a.lds_X1;
+  // result buffer of the y stages: single stage runs in place in Sb
+  cpx<T>* Yb = (a.ay.nst == 1 || (a.ay.nst & 1) == 0) ? Sb : Pb;
+
+  for (int r = 0; r < n1; ++r) {
+    if constexpr (S > 0) {
+      // fold
+      const int total = (nslab * m) << bcl;
+      for (int it = threadIdx.x; it < total; it += blockDim.x) {
+        const int bl = it & bmask;
+        const int rest = it >> bcl;
+        const int xi = rest / m, j2 = rest - xi * m;
+        cpx<T> acc = {0, 0};
+        for (int tt = 0; tt < n1; ++tt) {
+          const int y = j2 + m * tt;
+          const int c = colidx[xi * ny + y];
+          if (c >= 0) {
+            const cpx<T> v = colp[(c << bcl) + bl];
+            acc = cadd(acc, twmul<S>(v, twf, twfl, (y * r) % ny));
+          }
+        }
+        Sb[it] = acc;
+      }
+      __syncthreads();
+      // y stages (in place for one stage, else ping-pong Sb/Pb)
+      if (a.ay.nst == 1) {
+        stage_run<S, T>(nslab, m, a.ay.R[0], 1, twy, twyl, bcl, LdsSrc<T>{Sb, m, bcl},
+                        LdsDst<T>{Sb, m, bcl});
+      } else {
+        for (int st = 0; st < a.ay.nst; ++st) {
+          cpx<T>* from = (st & 1) ? Pb : Sb;
+          cpx<T>* to = (st & 1) ? Sb : Pb;
+          stage_run<S, T>(nslab, m, a.ay.R[st], a.ay.p[st], twy + a.ay.twoff[st],
+                          twyl ? twyl + a.ay.twoff[st] : twyl, bcl, LdsSrc<T>{from, m, bcl},
+                          LdsDst<T>{to, m, bcl});
+          if (st + 1 < a.ay.nst) __syncthreads();
+        }
+      }
+      __syncthreads();
+      // x transforms of the class's rows, lx rows at a time
+      cpx<T>* __restrict__ gout = reinterpret_cast<cpx<T>*>(a.out) + d.grid_off;
+      for (int rb = 0; rb < m; rb += a.lx) {
+        const int nrows = min(a.lx, m - rb);
+        auto gsrc = [=](int line, int x, int bl) -> cpx<T> {
+          const int xi = xinv[x];
+          if (xi >= 0) return Yb[((xi * m + rb + line) << bcl) + bl];
+          return cpx<T>{0, 0};
+        };
+        auto gdst = [=](int line, int x, int bl, cpx<T> v) {
+          const int y = r + n1 * (rb + line);
+          const int b = b0 + bl;
+          if (b < nb)
+            gout[(static_cast<int64_t>(z * ny + y) * nx + x) * nb + b] = v;
+        };
+        axis_run<S, T>(a.ax, nrows, twx, twxl, bcl, X0, X1, gsrc, gdst);
+        __syncthreads();
+      }
+    } else {
+      const cpx<T>* __restrict__ gin = reinterpret_cast<const cpx<T>*>(a.in) + d.grid_off;
+      for (int rb = 0; rb < m; rb += a.lx) {
+        const int nrows = min(a.lx, m - rb);
+        auto gsrc = [=](int line, int x, int bl) -> cpx<T> {
+          const int y = r + n1 * (rb + line);
+          const int b = b0 + bl;
+          if (b < nb) return gin[(static_cast<int64_t>(z * ny + y) * nx + x) * nb + b];
+          return cpx<T>{0, 0};
+        };
+        auto gdst = [=](int line, int x, int bl, cpx<T> v) {
+          const int xi = xinv[x];
+          if (xi >= 0) Sb[((xi * m + rb + line) << bcl) + bl] = v;
+        };
+        axis_run<S, T>(a.ax, nrows, twx, twxl, bcl, X0, X1, gsrc, gdst);
+        __syncthreads();
+      }
+      if (a.ay.nst == 1) {
+        stage_run<S, T>(nslab, m, a.ay.R[0], 1, twy, twyl, bcl, LdsSrc<T>{Sb, m, bcl},
+                        LdsDst<T>{Sb, m, bcl});
+      } else {
+        for (int st = 0; st < a.ay.nst; ++st) {
+          cpx<T>* from = (st & 1) ? Pb : Sb;
+          cpx<T>* to = (st & 1) ? Sb : Pb;
+          stage_run<S, T>(nslab, m, a.ay.R[st], a.ay.p[st], twy + a.ay.twoff[st],
+                          twyl ? twyl + a.ay.twoff[st] : twyl, bcl, LdsSrc<T>{from, m, bcl},
+                          LdsDst<T>{to, m, bcl});
+          if (st + 1 < a.ay.nst) __syncthreads();
+        }
+      }
+      __syncthreads();
+      // unfold into the columns
+      const int total = ncol << bcl;
+      for (int it = threadIdx.x; it < total; it += blockDim.x) {
+        const int bl = it & bmask;
+        const int c = it >> bcl;
+        const int xi = cxi[c], y = cy[c];
+        const int ym = y % m;
+        cpx<T> v = twmul<S>(Yb[((xi * m + ym) << bcl) + bl], twf, twfl, (y * r) % ny);
+        cpx<T>* p = colp + ((static_cast<int64_t>(c) << bcl) + bl);
+        if (r > 0) v = cadd(v, *p);
+        *p = v;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+template <int S, typename T>
+__global__ void __launch_bounds__(256) k1_kernel(const KArgs a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
+  if (!a.persistent) {
+    const int t = static_task(a.k1_tasks);
+    if (t >= 0) k1_task<S, T>(a, t, lds);
+    return;
+  }
+  __shared__ int sh_task;
+  for (;;) {
+    if (threadIdx.x == 0) sh_task = dynamic_task(a.counters, a.k1_tasks);
+    __syncthreads();
+    const int t = sh_task;
+    __syncthreads();
+    if (t < 0) break;
+    k1_task<S, T>(a, t, lds);
+    __syncthreads();
+  }
+}
+
+template <int S, typename T>
+__global__ void __launch_bounds__(256) k2_kernel(const KArgs a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
+  if (!a.persistent) {
+    const int t = static_task(a.k2_tasks);
+    if (t >= 0) k2_task<S, T>(a, t, lds);
+    return;
+  }
+  __shared__ int sh_task;
+  for (;;) {
+    if (threadIdx.x == 0) sh_task = dynamic_task(a.counters + 8, a.k2_tasks);
+    __syncthreads();
+    const int t = sh_task;
+    __syncthreads();
+    if (t < 0) break;
+    k2_task<S, T>(a, t, lds);
+    __syncthreads();
+  }
+}
+
+__global__ void reset_counters(unsigned int* c) {
+  if (threadIdx.x < 16) c[threadIdx.x] = 0u;
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers (called from the C ABI layer).
+template <int S, typename T>
+static hipError_t set_attrs(size_t lds1, size_t lds2) {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k1_kernel<S, T>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds1);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(k2_kernel<S, T>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2);
+}
+
+hipError_t prepare_kernels(bool fp64, size_t lds1, size_t lds2) {
+  hipError_t e = fp64 ? set_attrs<+1, double>(lds1, lds2) : set_attrs<+1, float>(lds1, lds2);
+  if (e != hipSuccess) return e;
+  return fp64 ? set_attrs<-1, double>(lds1, lds2) : set_attrs<-1, float>(lds1, lds2);
+}
+
+hipError_t launch_reset(unsigned int* counters, hipStream_t st) {
+  hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, st, counters);
+  return hipGetLastError();
+}
+
+// which: 1 = column kernel, 2 = plane kernel
+hipError_t launch_kernel(int which, const KArgs& a, bool inverse, bool fp64, int grid, int threads,
+                         size_t lds, hipStream_t st) {
+  if (which == 1) {
+    if (inverse) {
+      if (fp64) hipLaunchKernelGGL((k1_kernel<+1, double>), dim3(grid), dim3(threads), lds, st, a);
+      else hipLaunchKernelGGL((k1_kernel<+1, float>), dim3(grid), dim3(threads), lds, st, a);
+    } else {
+      if (fp64) hipLaunchKernelGGL((k1_kernel<-1, double>), dim3(grid), dim3(threads), lds, st, a);
+      else hipLaunchKernelGGL((k1_kernel<-1, float>), dim3(grid), dim3(threads), lds, st, a);
+    }
+  } else {
+    if (inverse) {
+      if (fp64) hipLaunchKernelGGL((k2_kernel<+1, double>), dim3(grid), dim3(threads), lds, st, a);
+      else hipLaunchKernelGGL((k2_kernel<+1, float>), dim3(grid), dim3(threads), lds, st, a);
+    } else {
+      if (fp64) hipLaunchKernelGGL((k2_kernel<-1, double>), dim3(grid), dim3(threads), lds, st, a);
+      else hipLaunchKernelGGL((k2_kernel<-1, float>), dim3(grid), dim3(threads), lds, st, a);
+    }
+  }
+  return hipGetLastError();
+}
+
+}  // namespace fftb

@@ -1,0 +1,146 @@
+"""CPU tests of the C ABI: the library loads, exports every symbol the header
+declares, validates its inputs and builds the offset-array tables. No compute
+call is made (host-only plans), so these run without a GPU."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+import paper_2406_05577_amd as pk
+from paper_2406_05577_amd import fftb as fb
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fftb.h")
+
+
+def header_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fftb_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = pk.lib()
+    names = header_functions()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(pk.EXPORTS) == names
+
+
+def host_plan(dims, maps, nb=2, dtype="c128", tuning=None):
+    return pk.Plan(dims, maps, nb, dtype=dtype, flags=pk.PLAN_HOST_ONLY, tuning=tuning)
+
+
+def test_status_strings():
+    L = pk.lib()
+    for s in (0, -1, -2, -3, -4):
+        assert L.fftb_status_string(s)
+    assert L.fftb_last_error() is not None
+
+
+@pytest.mark.parametrize("dims,semi,k", [((6, 5, 4), (1.6, 1.3, 1.1), (0.31, -0.22, 0.4)),
+                                        ((32, 32, 32), (8, 8, 8), (0, 0, 0)),
+                                        ((144, 160, 180), (36, 40, 45), (0.2, -0.1, 0.3))])
+def test_column_tables_match_map(dims, semi, k):
+    m, lin = synth.sphere_map(dims, semi, k)
+    rng = np.random.default_rng(0)
+    lin = lin[rng.permutation(lin.shape[0])]
+    p = host_plan(dims, [lin])
+    nx, ny, nz = dims
+    cx, cy, ec, ez = p.sphere_columns(0)
+    x = lin % nx
+    y = (lin // nx) % ny
+    z = lin // (nx * ny)
+    # columns = distinct (x, y) ordered by (x, y); entries point at their column and z
+    keys = sorted(set(zip(x.tolist(), y.tolist())))
+    assert list(zip(cx.tolist(), cy.tolist())) == keys
+    np.testing.assert_array_equal(cx[ec], x)
+    np.testing.assert_array_equal(cy[ec], y)
+    np.testing.assert_array_equal(ez, z)
+    ncol, nslab = p.sphere_stats(0)
+    assert ncol == len(keys) and nslab == len(set(x.tolist()))
+    assert p.info["total_coeffs"] == lin.shape[0]
+    assert p.info["grid_elems"] == nx * ny * nz * 2
+    assert p.info["sphere_elems"] == lin.shape[0] * 2
+
+
+def test_survey_shapes():
+    # occupied columns and slabs of the 128^3 |G|<=32 sphere
+    w = synth.make_workload("c2", nbands=1)
+    p = host_plan(w.dims, [w.spheres[0].lin], nb=256)
+    assert p.sphere_stats(0) == (3209, 65)
+
+
+def test_radix_plans():
+    for n, expect in [(128, [16, 8]), (32, [8, 4]), (96, [12, 8]), (144, [12, 12]),
+                      (160, [16, 10]), (180, [15, 12]), (4, [4]), (7 * 0 + 1, [1])]:
+        lin = np.array([0], np.int32)
+        p = host_plan((n, 4, 4), [lin])
+        assert p.info["radix_x"] == expect, (n, p.info["radix_x"])
+
+
+def _expect_status(status, fn):
+    with pytest.raises(pk.FftbError) as ei:
+        fn()
+    assert ei.value.status == status, str(ei.value)
+
+
+def test_validation_errors():
+    ok = np.array([0, 1, 2], np.int32)
+    _expect_status(pk.FFTB_ERR_UNSUPPORTED, lambda: host_plan((7, 4, 4), [ok]))
+    _expect_status(pk.FFTB_ERR_UNSUPPORTED, lambda: host_plan((4, 11, 4), [ok]))
+    _expect_status(pk.FFTB_ERR_INVALID, lambda: host_plan((4, 4, 4), [np.array([0, 0], np.int32)]))
+    _expect_status(pk.FFTB_ERR_INVALID, lambda: host_plan((4, 4, 4), [np.array([0, 64], np.int32)]))
+    _expect_status(pk.FFTB_ERR_INVALID, lambda: host_plan((4, 4, 4), [np.array([-1], np.int32)]))
+    _expect_status(pk.FFTB_ERR_INVALID, lambda: host_plan((4, 4, 4), [np.array([], np.int32)]))
+    _expect_status(pk.FFTB_ERR_INVALID, lambda: host_plan((4, 4, 4), [ok], nb=0))
+    _expect_status(pk.FFTB_ERR_INVALID, lambda: host_plan((0, 4, 4), [ok]))
+    _expect_status(pk.FFTB_ERR_INVALID, lambda: host_plan((4, 4, 4), [ok], tuning=dict(band_chunk=3)))
+    _expect_status(pk.FFTB_ERR_INVALID, lambda: host_plan((4, 4, 4), [ok], tuning=dict(y_classes=3)))
+    _expect_status(pk.FFTB_ERR_INVALID, lambda: host_plan((4, 4, 4), [ok], tuning=dict(threads=100)))
+
+
+def test_null_pointers():
+    L = pk.lib()
+    h = C.c_void_p()
+    d = (C.c_int32 * 3)(4, 4, 4)
+    m = np.array([0, 1], np.int32)
+    sp = (fb.Sphere_t * 1)()
+    sp[0].n_coeffs = 2
+    sp[0].map = m.ctypes.data_as(C.POINTER(C.c_int32))
+    sp[0].nbands = 1
+    assert L.fftb_plan_create(None, d, sp, 1, 0, pk.PLAN_HOST_ONLY, None, None) == pk.FFTB_ERR_INVALID
+    assert L.fftb_plan_create(C.byref(h), None, sp, 1, 0, pk.PLAN_HOST_ONLY, None, None) == pk.FFTB_ERR_INVALID
+    assert L.fftb_plan_create(C.byref(h), d, None, 1, 0, pk.PLAN_HOST_ONLY, None, None) == pk.FFTB_ERR_INVALID
+    assert L.fftb_plan_create(C.byref(h), d, sp, 0, 0, pk.PLAN_HOST_ONLY, None, None) == pk.FFTB_ERR_INVALID
+    assert L.fftb_plan_create(C.byref(h), d, sp, 1, 7, pk.PLAN_HOST_ONLY, None, None) == pk.FFTB_ERR_INVALID
+    sp[0].map = None
+    assert L.fftb_plan_create(C.byref(h), d, sp, 1, 0, pk.PLAN_HOST_ONLY, None, None) == pk.FFTB_ERR_INVALID
+    assert b"null map" in L.fftb_last_error()
+    sp[0].map = m.ctypes.data_as(C.POINTER(C.c_int32))
+    assert L.fftb_plan_create(C.byref(h), d, sp, 1, 0, pk.PLAN_HOST_ONLY, None, None) == 0
+    # a host-only plan refuses to execute; null data pointers are rejected
+    assert L.fftb_sphere_to_grid(h, C.c_void_p(16), C.c_void_p(16), None) == pk.FFTB_ERR_INVALID
+    assert L.fftb_grid_to_sphere(h, None, None, None) == pk.FFTB_ERR_INVALID
+    assert L.fftb_sphere_to_grid(None, None, None, None) == pk.FFTB_ERR_INVALID
+    info = fb.Info_t()
+    assert L.fftb_plan_get_info(None, C.byref(info)) == pk.FFTB_ERR_INVALID
+    assert L.fftb_plan_get_info(h, None) == pk.FFTB_ERR_INVALID
+    assert L.fftb_plan_sphere_stats(h, 5, None, None) == pk.FFTB_ERR_INVALID
+    assert L.fftb_plan_destroy(h) == 0
+    assert L.fftb_plan_destroy(None) == 0
+
+
+def test_tiling_fits_lds():
+    # every recipe gets a tiling whose LDS fits (checked inside the library)
+    for name in ("c1", "c2", "c3", "c4", "c5"):
+        w = synth.make_workload(name, nbands=1, nkpts=1)
+        for dt in ("c128", "c64"):
+            p = host_plan(w.dims, [w.spheres[0].lin], nb=synth.RECIPES[name]["nb"], dtype=dt)
+            t = p.info["tuning"]
+            assert w.dims[1] % t["y_classes"] == 0
+            assert t["band_chunk"] & (t["band_chunk"] - 1) == 0

@@ -1,0 +1,83 @@
+"""GPU parity: the HIP path against the FP64 oracle, element by element.
+
+Bars: relative L2 error <= 1e-12 for complex128 and <= 5e-6 for complex64
+(E_inv: grid vs oracle inverse; E_fwd: GPU forward of the oracle grid vs the
+oracle forward; E_rt: GPU round trip vs the input). Outputs start as NaN so an
+element the kernels never write fails the check.
+"""
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import TOL, check_workload
+
+pytestmark = pytest.mark.gpu
+
+# dims, semi-axes, k-points, bands, seed -- mixed radix, ellipsoids, k != 0,
+# ragged band counts (odd Nb exercises band-chunk tails)
+CASES = [
+    ((6, 5, 4), (1.6, 1.3, 1.1), [(0.31, -0.22, 0.4)], 3, 1),
+    ((12, 10, 15), (3.9, 3.2, 5.1), [(0.2, 0.35, -0.41), (-0.1, 0.0, 0.3)], 7, 2),
+    ((8, 9, 10), (2.7, 3.1, 2.2), [(-0.45, 0.12, 0.05)], 1, 3),
+    ((4, 4, 4), (1, 1, 1), [(0.0, 0.0, 0.0)], 5, 4),
+    ((16, 18, 20), (4.2, 4.4, 4.9), [(0.1, -0.3, 0.2)], 17, 5),
+    ((30, 24, 36), (7.1, 5.9, 8.8), [(0.05, 0.4, -0.2), (0.3, 0.3, 0.3), (0, 0, 0)], 9, 6),
+]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_small_default(case, dtype):
+    dims, semi, kpts, nb, seed = CASES[case]
+    w = synth.small_workload(dims, semi, kpts, nb, seed=seed, shuffle=(case % 2 == 1))
+    e = check_workload(w, dtype)
+    print(case, dtype, e)
+    assert max(e) <= TOL[dtype], e
+
+
+TUNINGS = [
+    dict(band_chunk=1), dict(band_chunk=2, threads=64), dict(band_chunk=4, col_tile=3),
+    dict(band_chunk=16, threads=128), dict(y_classes=2, x_rows=1), dict(y_classes=5, x_rows=2),
+    dict(y_classes=10), dict(band_chunk=8, y_classes=1, x_rows=1, col_tile=1),
+]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("ti", range(len(TUNINGS)))
+def test_tunings(ti, dtype):
+    dims, semi, kpts, nb, seed = CASES[1]
+    w = synth.small_workload(dims, semi, kpts, nb, seed=seed, shuffle=True)
+    e = check_workload(w, dtype, tuning=TUNINGS[ti])
+    assert max(e) <= TOL[dtype], (TUNINGS[ti], e)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("flags", [1, 4, 5])
+def test_batched_and_graph(flags, dtype):
+    dims, semi, kpts, nb, seed = CASES[5]
+    w = synth.small_workload(dims, semi, kpts, nb, seed=seed)
+    e = check_workload(w, dtype, flags=flags, reps=3)
+    assert max(e) <= TOL[dtype], (flags, e)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_forward_not_band_limited(dtype):
+    dims, semi, kpts, nb, seed = CASES[4]
+    w = synth.small_workload(dims, semi, kpts, nb, seed=seed)
+    g = [synth.random_grid(np.random.default_rng(99), dims, nb)]
+    e = check_workload(w, dtype, grid_in=g)
+    assert e[1] <= TOL[dtype], e
+
+
+def test_c1_full():
+    w = synth.make_workload("c1")
+    e = check_workload(w, "c128")
+    print("c1", e)
+    assert max(e) <= 1e-12, e
+
+
+def test_c3alt_full():
+    w = synth.make_workload("c3alt")
+    e = check_workload(w, "c64")
+    print("c3alt", e)
+    assert max(e) <= 5e-6, e
