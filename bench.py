@@ -47,7 +47,7 @@ DESCR = {
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("kernels.hip", "api.cpp", "plan.cpp"):
+    for f in ("kernels.hip", "kernels_reg.hip", "device_common.hpp", "api.cpp", "plan.cpp"):
         with open(os.path.join(ROOT, "paper_2406_05577_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

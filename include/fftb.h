@@ -69,7 +69,9 @@ typedef enum {
 enum {
   FFTB_PLAN_PLAIN = 0,       /* one launch per kernel per call, grid sized to the work */
   FFTB_PLAN_BATCHED = 1,     /* persistent kernels walking a device work list over all spheres */
-  FFTB_PLAN_AUTOTUNE = 2,    /* time candidate tilings at create time and keep the fastest */
+  FFTB_PLAN_AUTOTUNE = 2,    /* time candidate tilings at create time and keep the fastest per
+                                direction; results are cached in the file named by the
+                                FFTB_TUNE_CACHE environment variable (default: none) */
   FFTB_PLAN_GRAPH = 4,       /* replay each direction as a captured hipGraph */
   FFTB_PLAN_HOST_ONLY = 8,   /* build and validate the host tables only; no device work (testing) */
   FFTB_PLAN_MFMA = 16        /* FFTB_C64 only: radix-16 stages as FP32 MFMA dense products */
@@ -87,13 +89,23 @@ typedef struct {
   int32_t nbands;      /* >= 1 bands sharing this map */
 } fftb_sphere;
 
-/* Tiling knobs. A zero field means "library default". */
+/* Tiling of one direction. A zero field means "library default". */
 typedef struct {
   int32_t band_chunk;   /* bands per workgroup tile, power of two, 1..64 */
-  int32_t y_classes;    /* n1: the plane kernel splits the y outputs into n1 residue classes; divides ny */
-  int32_t x_rows;       /* rows per x-transform batch in the plane kernel */
-  int32_t col_tile;     /* columns per workgroup in the column kernel */
-  int32_t threads;      /* threads per workgroup: 64, 128, 256, 512 or 1024 */
+  int32_t y_classes;    /* n1: the plane kernel splits the y index into n1 residue classes; divides ny */
+  int32_t x_rows;       /* rows per x-transform batch (LDS-stage path only) */
+  int32_t col_tile;     /* columns per column-kernel task */
+  int32_t threads;      /* plane-kernel workgroup size: 64, 128, 256 or 512 */
+  int32_t path;         /* 0 = choose, 1 = LDS-stage kernels, 2 = register-line kernels */
+  int32_t acc;          /* forward only: 0 = choose, 1 = column accumulators in LDS (the plane's
+                           columns split over workgroups), 2 = accumulators in global memory */
+  int32_t splits;       /* forward only: column splits per (plane, chunk), 1..8 */
+} fftb_dir_tuning;
+
+/* Tiling knobs of both directions (they are chosen and tuned independently). */
+typedef struct {
+  fftb_dir_tuning inv;  /* sphere_to_grid */
+  fftb_dir_tuning fwd;  /* grid_to_sphere */
 } fftb_tuning;
 
 /* Summary of a plan. */
@@ -111,6 +123,7 @@ typedef struct {
   int64_t workspace_bytes;     /* device scratch + tables held by the plan */
   int32_t radix_x[8], radix_y[8], radix_z[8]; /* per-axis radix plan, 0-terminated */
   fftb_tuning tuning;          /* the tiling in use */
+  int32_t autotuned;           /* 1 if the tiling came from timed trials, 2 if from the tuning cache */
 } fftb_plan_info;
 
 /*

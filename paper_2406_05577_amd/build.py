@@ -13,7 +13,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libfftb.so")
 
-SOURCES = ["plan.cpp", "api.cpp", "kernels.hip"]
+SOURCES = ["plan.cpp", "api.cpp", "kernels.hip", "kernels_reg.hip"]
 
 # Packed FP32 instructions are disabled for all device code; the host pass
 # warns that it does not know the feature, which is harmless.

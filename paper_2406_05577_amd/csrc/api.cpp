@@ -26,9 +26,16 @@ hipError_t prepare_kernels(bool fp64, size_t lds1, size_t lds2);
 hipError_t launch_reset(unsigned int* counters, hipStream_t st);
 hipError_t launch_kernel(int which, const KArgs& a, bool inverse, bool fp64, int grid, int threads,
                          size_t lds, hipStream_t st);
+bool reg_shape_supported(bool fp64, int E, int H);
+hipError_t launch_reg(int which, const KArgs& a, bool inverse, bool fp64, int E, int H, int grid,
+                      int threads, size_t lds, hipStream_t st);
+hipError_t prepare_reg(bool fp64, int E, int H, size_t lds);
 }  // namespace fftb
 
 using namespace fftb;
+
+extern "C" fftb_status fftb_plan_create(fftb_plan*, const int32_t[3], const fftb_sphere*, int32_t,
+                                        fftb_dtype, uint32_t, const fftb_tuning*, void*);
 
 namespace {
 
@@ -46,6 +53,28 @@ struct DevBuf {
   size_t bytes = 0;
 };
 
+// Tiling and task decomposition of one direction.
+struct DirCfg {
+  int bc = 8, n1 = 1, m = 1, lx = 1, lc = 1, threads = 256;
+  bool reg1 = false, reg2 = false;  // register path for the column / plane kernel
+  int e1 = 0, h1 = 0, e2 = 0, h2 = 0;
+  bool class_par = false;           // plane tasks include the y class
+  bool acc_lds = false;             // forward accumulators in LDS
+  int nsplit = 1;                   // forward plane tasks per (plane, chunk)
+  std::vector<int32_t> splits;      // per sphere nsplit+1 slab boundaries
+  int sx = 0;
+  size_t lds1 = 0, lds2 = 0;
+  int lds_P = 0, lds_X0 = 0, lds_X1 = 0, lds_acc = 0;
+  AxisPlan ay;                      // y plan of length m
+  std::vector<SphereDesc> desc;
+  int k1_tasks = 0, k2_tasks = 0;
+  int64_t col_elems = 0;
+  SphereDesc* d_desc = nullptr;
+  int32_t* d_splits = nullptr;
+  void* d_twy = nullptr;
+  void* d_twy_lo = nullptr;
+};
+
 }  // namespace
 
 struct fftb_plan_s {
@@ -53,24 +82,22 @@ struct fftb_plan_s {
   fftb_dtype dtype = FFTB_C128;
   uint32_t flags = 0;
   std::vector<SphereTables> sph;
-  std::vector<SphereDesc> desc;
-  AxisPlan ax, ay, az;  // ay is the plan of the class length m
+  AxisPlan ax, az;
+  DirCfg dir[2];  // 0 = inverse (sphere_to_grid), 1 = forward
   fftb_tuning tun = {};
-  int k1_tasks = 0, k2_tasks = 0;
-  size_t lds1 = 0, lds2 = 0;
-  int lds_P = 0, lds_X0 = 0, lds_X1 = 0;
-  int64_t sphere_elems = 0, grid_elems = 0, col_elems = 0;
+  int64_t sphere_elems = 0, grid_elems = 0;
   int64_t total_coeffs = 0, total_columns = 0;
   int max_ncol = 0, max_nslab = 0;
+  int autotuned = 0;
   bool device = false;
   int num_cus = 256;
   // device memory
   std::vector<DevBuf> bufs;
-  SphereDesc* d_desc = nullptr;
   int32_t *d_gidx = nullptr, *d_colidx = nullptr, *d_colxi = nullptr, *d_coly = nullptr,
-          *d_xinv = nullptr;
-  void *d_twx = nullptr, *d_twy = nullptr, *d_twz = nullptr, *d_twf = nullptr;
-  void *d_twx_lo = nullptr, *d_twy_lo = nullptr, *d_twz_lo = nullptr, *d_twf_lo = nullptr;
+          *d_xinv = nullptr, *d_slabstart = nullptr;
+  void *d_twx = nullptr, *d_twz = nullptr, *d_twf = nullptr;
+  void *d_twx_lo = nullptr, *d_twz_lo = nullptr, *d_twf_lo = nullptr;
+  void *d_rootx = nullptr, *d_rootx_lo = nullptr, *d_rootz = nullptr, *d_rootz_lo = nullptr;
   void* d_col = nullptr;
   unsigned int* d_counters = nullptr;
   size_t dev_bytes = 0;
@@ -82,7 +109,7 @@ struct fftb_plan_s {
     void* out = nullptr;
   } gc[2];
   hipStream_t cap_stream = nullptr;
-  // per-kernel timing (FFTB profiling)
+  // per-kernel timing
   bool profiling = false;
   struct ProfRec {
     int kid;
@@ -112,20 +139,40 @@ struct fftb_plan_s {
 namespace {
 
 int es_of(fftb_dtype dt) { return dt == FFTB_C128 ? 16 : 8; }
-
 int nbuf_of(int nst) { return nst >= 3 ? 2 : (nst == 2 ? 1 : 0); }
-
 int ilog2(int v) {
   int l = 0;
   while ((1 << l) < v) ++l;
   return l;
 }
-
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+bool single_codelet(int m) {
+  switch (m) {
+    case 1: case 2: case 3: case 4: case 5: case 6: case 8: case 9: case 10: case 12: case 15:
+    case 16:
+      return true;
+  }
+  return false;
+}
 
-// LDS bytes of the plane kernel for a given class count n1 and x batch lx.
-bool plane_lds(const fftb_plan_s& P, int n1, int bc, int lx, size_t& bytes, int& offP, int& offX0,
-               int& offX1, AxisPlan& aym) {
+// Register shape (E values per lane, H lanes per line) for a line of length n.
+bool reg_shape(int n, bool fp64, int& E, int& H) {
+  (void)fp64;
+  const int hmax = 8;
+  for (int h = hmax; h >= 1; h >>= 1) {
+    if (n % h) continue;
+    if (reg_shape_supported(fp64, n / h, h)) {
+      E = n / h;
+      H = h;
+      return true;
+    }
+  }
+  return false;
+}
+
+// LDS bytes of the LDS-stage plane kernel for class count n1 and x batch lx.
+bool plane_lds_generic(const fftb_plan_s& P, int n1, int bc, int lx, size_t& bytes, int& offP,
+                       int& offX0, int& offX1, AxisPlan& aym) {
   const int m = P.ny / n1;
   std::vector<int> rad;
   if (!plan_radices(m, rad)) return false;
@@ -137,47 +184,178 @@ bool plane_lds(const fftb_plan_s& P, int n1, int bc, int lx, size_t& bytes, int&
   offP = static_cast<int>(S);
   offX0 = static_cast<int>(S + Pn);
   offX1 = static_cast<int>(S + Pn + (nbx >= 1 ? X : 0));
-  const int64_t tot = S + Pn + nbx * X;
-  bytes = static_cast<size_t>(tot) * es_of(P.dtype);
+  bytes = static_cast<size_t>(S + Pn + nbx * X) * es_of(P.dtype);
   return true;
 }
 
-fftb_status choose_tiling(fftb_plan_s& P, const fftb_tuning* user) {
-  const int es = es_of(P.dtype);
+// LDS of the register-path plane kernel: the class slab (nslab lines of m
+// values for bc bands, line stride padded by one element) plus, in the forward
+// direction with accumulators in LDS, ncol x bc accumulators.
+size_t plane_lds_reg(const fftb_plan_s& P, int m, int bc, bool acc, int& sx, int& off_acc) {
+  sx = m * bc + 1;
+  const int64_t S = static_cast<int64_t>(P.max_nslab) * sx;
+  off_acc = static_cast<int>(S);
+  const int64_t A = acc ? static_cast<int64_t>(P.max_ncol) * bc : 0;
+  return static_cast<size_t>(S + A) * es_of(P.dtype);
+}
+
+// Cut a sphere's slabs into Q contiguous ranges with about equal column counts.
+void split_slabs(const SphereTables& sp, int Q, std::vector<int32_t>& cuts) {
+  cuts.assign(Q + 1, sp.nslab);
+  cuts[0] = 0;
+  int q = 1;
+  for (int xi = 0; xi < sp.nslab && q < Q; ++xi) {
+    // cut after slab xi once the columns so far reach q/Q of the total
+    if (static_cast<int64_t>(sp.slabstart[xi + 1]) * Q >= static_cast<int64_t>(sp.ncol) * q) {
+      cuts[q++] = xi + 1;
+    }
+  }
+  for (; q < Q; ++q) cuts[q] = sp.nslab;
+}
+
+int default_bc(const fftb_plan_s& P, int want) {
   int maxnb = 1;
   for (auto& s : P.sph) maxnb = std::max(maxnb, s.nb);
-  fftb_tuning t = {};
-  if (user) t = *user;
-  // band chunk
+  int cap = 1;
+  while (cap < maxnb) cap <<= 1;
+  return std::min(want, cap);
+}
+
+fftb_status choose_dir(fftb_plan_s& P, int d, const fftb_dir_tuning& t) {
+  DirCfg& D = P.dir[d];
+  const bool fp64 = P.dtype == FFTB_C128;
+  const bool inverse = d == 0;
+  const int es = es_of(P.dtype);
   int bc = t.band_chunk;
-  if (bc == 0) {
-    bc = (P.dtype == FFTB_C128) ? 8 : 16;
-    int cap = 1;
-    while (cap < maxnb) cap <<= 1;
-    bc = std::min(bc, cap);
-  }
+  int n1 = t.y_classes;
+  if (bc == 0) bc = default_bc(P, fp64 ? 8 : 16);
   if (!is_pow2(bc) || bc > 64)
     return fail(FFTB_ERR_INVALID, "band_chunk must be a power of two in [1, 64]");
   int threads = t.threads ? t.threads : 256;
-  if (threads != 64 && threads != 128 && threads != 256)
-    return fail(FFTB_ERR_INVALID, "threads must be 64, 128 or 256");
-  // column kernel tile
-  const int nbz = nbuf_of(P.az.nst);
-  int lc = t.col_tile;
-  if (lc == 0) {
-    if (nbz == 0) {
-      lc = 16;
-    } else {
-      const int64_t per = static_cast<int64_t>(nbz) * P.nz * bc * es;
-      lc = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(16, (64 * 1024) / per)));
+  if (threads != 64 && threads != 128 && threads != 256 && threads != 512)
+    return fail(FFTB_ERR_INVALID, "threads must be 64, 128, 256 or 512");
+  if (n1 != 0 && (n1 < 1 || P.ny % n1)) return fail(FFTB_ERR_INVALID, "y_classes must divide ny");
+  if (t.path < 0 || t.path > 2) return fail(FFTB_ERR_INVALID, "path must be 0, 1 or 2");
+  if (t.acc < 0 || t.acc > 2) return fail(FFTB_ERR_INVALID, "acc must be 0, 1 or 2");
+  if (t.splits < 0 || t.splits > 8) return fail(FFTB_ERR_INVALID, "splits must be in [1, 8]");
+  if (t.col_tile < 0) return fail(FFTB_ERR_INVALID, "col_tile must be >= 1");
+  if (t.x_rows < 0) return fail(FFTB_ERR_INVALID, "x_rows must be >= 1");
+  D.bc = bc;
+  D.threads = threads;
+  // ---- column kernel
+  int e1 = 0, h1 = 0;
+  D.reg1 = t.path != 1 && reg_shape(P.nz, fp64, e1, h1);
+  D.e1 = e1;
+  D.h1 = h1;
+  if (D.reg1) {
+    D.lc = t.col_tile ? t.col_tile : std::max(1, 512 / (bc * h1));
+    D.lds1 = 0;
+  } else {
+    const int nbz = nbuf_of(P.az.nst);
+    int lc = t.col_tile;
+    if (lc == 0) {
+      if (nbz == 0) {
+        lc = 16;
+      } else {
+        const int64_t per = static_cast<int64_t>(nbz) * P.nz * bc * es;
+        lc = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(16, (64 * 1024) / per)));
+      }
     }
+    D.lc = lc;
+    D.lds1 = static_cast<size_t>(nbz) * lc * P.nz * bc * es;
   }
-  if (lc < 1) return fail(FFTB_ERR_INVALID, "col_tile must be >= 1");
-  P.lds1 = static_cast<size_t>(nbz) * lc * P.nz * bc * es;
-  if (P.lds1 > kLdsMax)
-    return fail(FFTB_ERR_UNSUPPORTED, "column kernel tile does not fit in LDS");
-  // plane kernel: residue classes and x batch
-  int n1 = t.y_classes, lx = t.x_rows;
+  if (D.lds1 > kLdsMax) return fail(FFTB_ERR_UNSUPPORTED, "column kernel tile does not fit in LDS");
+  // ---- plane kernel, register path
+  int e2 = 0, h2 = 0;
+  D.reg2 = false;
+  if (t.path != 1 && reg_shape(P.nx, fp64, e2, h2)) {
+    if (inverse) {
+      // class-parallel tasks; the class slab must fit (aim for two workgroups per CU
+      // unless the class count is fixed)
+      const size_t cap = n1 ? kLdsMax : kLdsMax / 2;
+      for (int c = 1; c <= P.ny; ++c) {
+        if (P.ny % c || (n1 && c != n1)) continue;
+        const int m = P.ny / c;
+        if (!single_codelet(m)) continue;
+        int sx, oa;
+        const size_t b = plane_lds_reg(P, m, bc, false, sx, oa);
+        if (b > cap) continue;
+        D.reg2 = true;
+        D.n1 = c;
+        D.m = m;
+        D.lds2 = b;
+        D.sx = sx;
+        D.class_par = true;
+        break;
+      }
+    } else {
+      // forward: the plane's columns are split into nsplit slab ranges whose
+      // accumulators (LDS) and class slab fit; each split redoes the x transform of
+      // the class rows. Cost model: HBM segment efficiency x redundant x work x
+      // occupancy; global accumulators (no split) are the fallback.
+      double best = 1e30;
+      const int bc_lo = t.band_chunk ? bc : std::max(1, bc / 2);
+      for (int b = bc; b >= bc_lo; b >>= 1) {
+        const int seg = b * es;
+        const double eff = seg >= 128 ? 1.0 : seg >= 64 ? 1.1 : seg >= 32 ? 1.5 : 3.0;
+        for (int c = 1; c <= P.ny; ++c) {
+          if (P.ny % c || (n1 && c != n1)) continue;
+          const int m = P.ny / c;
+          if (!single_codelet(m)) continue;
+          for (int Q = t.splits ? t.splits : 1; Q <= 8; ++Q) {
+            if (t.acc == 2 && Q > 1) break;
+            int max_sl = 0, max_cl = 0;
+            for (auto& sp : P.sph) {
+              std::vector<int32_t> cuts;
+              split_slabs(sp, Q, cuts);
+              for (int q = 0; q < Q; ++q) {
+                max_sl = std::max(max_sl, cuts[q + 1] - cuts[q]);
+                max_cl = std::max(max_cl, sp.slabstart[cuts[q + 1]] - sp.slabstart[cuts[q]]);
+              }
+            }
+            const int sx = m * b + 1;
+            const bool acc = t.acc != 2;
+            const size_t bytes = (static_cast<size_t>(max_sl) * sx +
+                                  (acc ? static_cast<size_t>(max_cl) * b : 0)) * es;
+            if (bytes > kLdsMax) continue;
+            const double cost = eff * (1.0 + 0.12 * (Q - 1)) * (bytes > kLdsMax / 2 ? 1.15 : 1.0) *
+                                (acc ? 1.0 : 4.0);
+            if (cost < best) {
+              best = cost;
+              D.reg2 = true;
+              D.bc = b;
+              D.n1 = c;
+              D.m = m;
+              D.nsplit = Q;
+              D.acc_lds = acc;
+              D.sx = sx;
+              D.lds_acc = max_sl * sx;
+              D.lds2 = bytes;
+              D.class_par = false;
+            }
+            break;  // larger Q only adds work once this one fits
+          }
+        }
+      }
+      if (D.reg2) bc = D.bc;
+    }
+    if (D.reg2) {
+      D.e2 = e2;
+      D.h2 = h2;
+      std::vector<int> rad;
+      plan_radices(D.m, rad);
+      make_axis_plan(D.m, rad, D.ay);
+      if (D.reg1 && !t.col_tile) D.lc = std::max(1, 512 / (bc * h1));
+    } else if (t.path == 2) {
+      return fail(FFTB_ERR_UNSUPPORTED, "no register-path class split fits in LDS");
+    }
+  } else if (t.path == 2) {
+    return fail(FFTB_ERR_UNSUPPORTED, "x length has no register-path shape");
+  }
+  if (t.path == 2 && !D.reg1) return fail(FFTB_ERR_UNSUPPORTED, "z length has no register-path shape");
+  if (D.reg2) return FFTB_OK;
+  // ---- plane kernel, LDS-stage path
+  int lx = t.x_rows;
   AxisPlan aym;
   size_t bytes = 0;
   int offP = 0, offX0 = 0, offX1 = 0;
@@ -187,7 +365,7 @@ fftb_status choose_tiling(fftb_plan_s& P, const fftb_tuning* user) {
       if (P.ny % c) continue;
       const int m = P.ny / c;
       const int want = std::min(m, lx ? lx : 2);
-      if (!plane_lds(P, c, bc, want, bytes, offP, offX0, offX1, aym)) continue;
+      if (!plane_lds_generic(P, c, bc, want, bytes, offP, offX0, offX1, aym)) continue;
       if (bytes <= kLdsMax) {
         n1 = c;
         break;
@@ -195,34 +373,31 @@ fftb_status choose_tiling(fftb_plan_s& P, const fftb_tuning* user) {
     }
     if (n1 < 0) return fail(FFTB_ERR_UNSUPPORTED, "no y-class split fits the plane in LDS");
   }
-  if (n1 < 1 || P.ny % n1) return fail(FFTB_ERR_INVALID, "y_classes must divide ny");
   const int m = P.ny / n1;
   if (lx == 0) {
-    // as many rows per batch as fit (all rows if the x plan is one stage)
     lx = 1;
     for (int c = m; c >= 1; --c) {
-      if (!plane_lds(P, n1, bc, c, bytes, offP, offX0, offX1, aym)) break;
+      if (!plane_lds_generic(P, n1, bc, c, bytes, offP, offX0, offX1, aym)) break;
       if (bytes <= kLdsMax / 2 || c == 1) {
         lx = c;
         break;
       }
     }
   }
-  if (lx < 1) return fail(FFTB_ERR_INVALID, "x_rows must be >= 1");
   lx = std::min(lx, m);
-  if (!plane_lds(P, n1, bc, lx, bytes, offP, offX0, offX1, aym))
+  if (!plane_lds_generic(P, n1, bc, lx, bytes, offP, offX0, offX1, aym))
     return fail(FFTB_ERR_UNSUPPORTED, "class length has an unsupported factor");
   if (bytes > kLdsMax) return fail(FFTB_ERR_UNSUPPORTED, "plane kernel tile does not fit in LDS");
-  P.ay = aym;
-  P.lds2 = bytes;
-  P.lds_P = offP;
-  P.lds_X0 = offX0;
-  P.lds_X1 = offX1;
-  P.tun.band_chunk = bc;
-  P.tun.y_classes = n1;
-  P.tun.x_rows = lx;
-  P.tun.col_tile = lc;
-  P.tun.threads = threads;
+  D.n1 = n1;
+  D.m = m;
+  D.lx = lx;
+  D.ay = aym;
+  D.lds2 = bytes;
+  D.lds_P = offP;
+  D.lds_X0 = offX0;
+  D.lds_X1 = offX1;
+  D.class_par = false;
+  D.acc_lds = false;
   return FFTB_OK;
 }
 
@@ -237,13 +412,14 @@ void fill_axis(const AxisPlan& a, AxisDev& d) {
   }
 }
 
-// Build the per-sphere descriptors and task ranges for the current tiling.
-void build_descs(fftb_plan_s& P) {
-  const int bc = P.tun.band_chunk;
+// Per-sphere descriptors and task ranges of one direction.
+void build_descs(fftb_plan_s& P, DirCfg& D) {
+  const int bc = D.bc;
   const int64_t N = static_cast<int64_t>(P.nx) * P.ny * P.nz;
-  P.desc.clear();
+  D.desc.clear();
+  D.splits.clear();
   int64_t soff = 0, goff = 0, coff = 0;
-  int32_t gi = 0, ci = 0, cm = 0, xo = 0;
+  int32_t gi = 0, ci = 0, cm = 0, xo = 0, so = 0;
   int k1 = 0, k2 = 0;
   for (auto& s : P.sph) {
     SphereDesc d = {};
@@ -254,15 +430,20 @@ void build_descs(fftb_plan_s& P) {
     d.colidx_off = ci;
     d.colmeta_off = cm;
     d.xinv_off = xo;
+    d.slab_off = so;
     d.ncol = s.ncol;
     d.nslab = s.nslab;
     d.nb = s.nb;
     d.nchunk = (s.nb + bc - 1) / bc;
     d.k1_start = k1;
-    k1 += ((s.ncol + P.tun.col_tile - 1) / P.tun.col_tile) * d.nchunk;
+    k1 += ((s.ncol + D.lc - 1) / D.lc) * d.nchunk;
     d.k1_end = k1;
     d.k2_start = k2;
-    k2 += P.nz * d.nchunk;
+    k2 += P.nz * d.nchunk * (D.class_par ? D.n1 : D.nsplit);
+    d.split_off = static_cast<int32_t>(D.splits.size());
+    std::vector<int32_t> cuts;
+    split_slabs(s, D.nsplit, cuts);
+    D.splits.insert(D.splits.end(), cuts.begin(), cuts.end());
     d.k2_end = k2;
     soff += s.ns * s.nb;
     goff += N * s.nb;
@@ -271,11 +452,12 @@ void build_descs(fftb_plan_s& P) {
     ci += s.nslab * P.ny;
     cm += s.ncol;
     xo += P.nx;
-    P.desc.push_back(d);
+    so += s.nslab + 1;
+    D.desc.push_back(d);
   }
-  P.k1_tasks = k1;
-  P.k2_tasks = k2;
-  P.col_elems = coff;
+  D.k1_tasks = k1;
+  D.k2_tasks = k2;
+  D.col_elems = coff;
 }
 
 fftb_status dev_alloc(fftb_plan_s& P, size_t bytes, void** out) {
@@ -328,18 +510,24 @@ fftb_status device_setup(fftb_plan_s& P, hipStream_t st) {
   if (e != hipSuccess)
     return fail(FFTB_ERR_HIP, std::string("hipGetDeviceProperties: ") + hipGetErrorString(e));
   P.num_cus = prop.multiProcessorCount;
-  std::vector<int32_t> gidx, colidx, colxi, coly, xinv;
+  std::vector<int32_t> gidx, colidx, colxi, coly, xinv, slabstart;
   for (auto& s : P.sph) {
     gidx.insert(gidx.end(), s.gidx.begin(), s.gidx.end());
     colidx.insert(colidx.end(), s.colidx.begin(), s.colidx.end());
     colxi.insert(colxi.end(), s.col_xi.begin(), s.col_xi.end());
     coly.insert(coly.end(), s.col_y.begin(), s.col_y.end());
     xinv.insert(xinv.end(), s.xinv.begin(), s.xinv.end());
+    slabstart.insert(slabstart.end(), s.slabstart.begin(), s.slabstart.end());
   }
   fftb_status s;
   void* p;
-  if ((s = upload(P, P.desc, &p, st)) != FFTB_OK) return s;
-  P.d_desc = static_cast<SphereDesc*>(p);
+  for (auto& D : P.dir) {
+    if ((s = upload(P, D.desc, &p, st)) != FFTB_OK) return s;
+    D.d_desc = static_cast<SphereDesc*>(p);
+    if ((s = upload(P, D.splits, &p, st)) != FFTB_OK) return s;
+    D.d_splits = static_cast<int32_t*>(p);
+    if ((s = upload_tw(P, axis_twiddles(D.ay), &D.d_twy, &D.d_twy_lo, st)) != FFTB_OK) return s;
+  }
   if ((s = upload(P, gidx, &p, st)) != FFTB_OK) return s;
   P.d_gidx = static_cast<int32_t*>(p);
   if ((s = upload(P, colidx, &p, st)) != FFTB_OK) return s;
@@ -350,19 +538,36 @@ fftb_status device_setup(fftb_plan_s& P, hipStream_t st) {
   P.d_coly = static_cast<int32_t*>(p);
   if ((s = upload(P, xinv, &p, st)) != FFTB_OK) return s;
   P.d_xinv = static_cast<int32_t*>(p);
+  if ((s = upload(P, slabstart, &p, st)) != FFTB_OK) return s;
+  P.d_slabstart = static_cast<int32_t*>(p);
   if ((s = upload_tw(P, axis_twiddles(P.ax), &P.d_twx, &P.d_twx_lo, st)) != FFTB_OK) return s;
-  if ((s = upload_tw(P, axis_twiddles(P.ay), &P.d_twy, &P.d_twy_lo, st)) != FFTB_OK) return s;
   if ((s = upload_tw(P, axis_twiddles(P.az), &P.d_twz, &P.d_twz_lo, st)) != FFTB_OK) return s;
   if ((s = upload_tw(P, root_table(P.ny), &P.d_twf, &P.d_twf_lo, st)) != FFTB_OK) return s;
-  if ((s = dev_alloc(P, static_cast<size_t>(P.col_elems) * es_of(P.dtype), &P.d_col)) != FFTB_OK)
+  if ((s = upload_tw(P, root_table(P.nx), &P.d_rootx, &P.d_rootx_lo, st)) != FFTB_OK) return s;
+  if ((s = upload_tw(P, root_table(P.nz), &P.d_rootz, &P.d_rootz_lo, st)) != FFTB_OK) return s;
+  const int64_t col_elems = std::max(P.dir[0].col_elems, P.dir[1].col_elems);
+  if ((s = dev_alloc(P, static_cast<size_t>(col_elems) * es_of(P.dtype), &P.d_col)) != FFTB_OK)
     return s;
   if ((s = dev_alloc(P, 16 * sizeof(unsigned int), &p)) != FFTB_OK) return s;
   P.d_counters = static_cast<unsigned int*>(p);
   e = hipMemsetAsync(P.d_counters, 0, 16 * sizeof(unsigned int), st);
   if (e != hipSuccess) return fail(FFTB_ERR_HIP, std::string("hipMemsetAsync: ") + hipGetErrorString(e));
-  e = prepare_kernels(P.dtype == FFTB_C128, std::max<size_t>(P.lds1, 4), std::max<size_t>(P.lds2, 4));
+  const bool fp64 = P.dtype == FFTB_C128;
+  size_t g1 = 4, g2 = 4, r2 = 4;
+  for (auto& D : P.dir) {
+    if (!D.reg1) g1 = std::max(g1, D.lds1);
+    if (!D.reg2) g2 = std::max(g2, D.lds2);
+    else r2 = std::max(r2, D.lds2);
+  }
+  e = prepare_kernels(fp64, g1, g2);
   if (e != hipSuccess)
     return fail(FFTB_ERR_HIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
+  for (auto& D : P.dir) {
+    if (!D.reg2) continue;
+    e = prepare_reg(fp64, D.e2, D.h2, r2);
+    if (e != hipSuccess)
+      return fail(FFTB_ERR_HIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
+  }
   e = hipStreamSynchronize(st);
   if (e != hipSuccess)
     return fail(FFTB_ERR_HIP, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
@@ -370,62 +575,75 @@ fftb_status device_setup(fftb_plan_s& P, hipStream_t st) {
   return FFTB_OK;
 }
 
-KArgs make_args(const fftb_plan_s& P, const void* in, void* out, bool inverse) {
+KArgs make_args(const fftb_plan_s& P, const DirCfg& D, const void* in, void* out, bool inverse) {
   KArgs a;
   std::memset(&a, 0, sizeof a);
   a.nx = P.nx;
   a.ny = P.ny;
   a.nz = P.nz;
-  a.bcl = ilog2(P.tun.band_chunk);
-  a.n1 = P.tun.y_classes;
-  a.m = P.ny / P.tun.y_classes;
-  a.lx = P.tun.x_rows;
-  a.lc = P.tun.col_tile;
+  a.bcl = ilog2(D.bc);
+  a.n1 = D.n1;
+  a.m = D.m;
+  a.lx = D.lx;
+  a.lc = D.lc;
   a.nsph = static_cast<int>(P.sph.size());
-  a.k1_tasks = P.k1_tasks;
-  a.k2_tasks = P.k2_tasks;
+  a.k1_tasks = D.k1_tasks;
+  a.k2_tasks = D.k2_tasks;
   a.persistent = (P.flags & FFTB_PLAN_BATCHED) ? 1 : 0;
-  a.lds_P = P.lds_P;
-  a.lds_X0 = P.lds_X0;
-  a.lds_X1 = P.lds_X1;
+  a.lds_P = D.lds_P;
+  a.lds_X0 = D.lds_X0;
+  a.lds_X1 = D.lds_X1;
+  a.lds_acc = D.lds_acc;
+  a.acc_lds = D.acc_lds ? 1 : 0;
+  a.sx = D.sx;
+  a.nsplit = D.nsplit;
+  a.splits = D.d_splits;
   fill_axis(P.ax, a.ax);
-  fill_axis(P.ay, a.ay);
+  fill_axis(D.ay, a.ay);
   fill_axis(P.az, a.az);
-  a.sph = P.d_desc;
+  a.sph = D.d_desc;
   a.gidx = P.d_gidx;
   a.colidx = P.d_colidx;
   a.col_xi = P.d_colxi;
   a.col_y = P.d_coly;
   a.xinv = P.d_xinv;
+  a.slabstart = P.d_slabstart;
   a.twx = P.d_twx;
-  a.twy = P.d_twy;
+  a.twy = D.d_twy;
   a.twz = P.d_twz;
   a.twf = P.d_twf;
   a.twx_lo = P.d_twx_lo;
-  a.twy_lo = P.d_twy_lo;
+  a.twy_lo = D.d_twy_lo;
   a.twz_lo = P.d_twz_lo;
   a.twf_lo = P.d_twf_lo;
+  a.rootx = P.d_rootx;
+  a.rootx_lo = P.d_rootx_lo;
+  a.rootz = P.d_rootz;
+  a.rootz_lo = P.d_rootz_lo;
   a.in = in;
   a.out = out;
   a.col = P.d_col;
   a.scale = inverse ? 1.0 : 1.0 / (static_cast<double>(P.nx) * P.ny * P.nz);
   a.counters = P.d_counters;
-  (void)inverse;
   return a;
 }
 
-void grids(const fftb_plan_s& P, int& g1, int& g2) {
+int occupancy(size_t lds) {
+  const int by_lds = lds > 0 ? std::max<int>(1, static_cast<int>(kLdsMax / lds)) : 8;
+  return std::min(by_lds, 8);
+}
+
+void grids(const fftb_plan_s& P, const DirCfg& D, int& g1, int& g2) {
+  g1 = ((D.k1_tasks + 7) / 8) * 8;
+  g2 = ((D.k2_tasks + 7) / 8) * 8;
   if (P.flags & FFTB_PLAN_BATCHED) {
     // persistent: enough blocks to fill the chip, at least one per XCD queue
-    const int occ1 = P.lds1 > 0 ? std::max<int>(1, static_cast<int>(kLdsMax / P.lds1)) : 8;
-    const int occ2 = P.lds2 > 0 ? std::max<int>(1, static_cast<int>(kLdsMax / P.lds2)) : 8;
-    g1 = std::max(8, std::min(P.num_cus * std::min(occ1, 8), ((P.k1_tasks + 7) / 8) * 8));
-    g2 = std::max(8, std::min(P.num_cus * std::min(occ2, 8), ((P.k2_tasks + 7) / 8) * 8));
+    const int c1 = P.num_cus * occupancy(D.lds1);
+    const int c2 = P.num_cus * occupancy(D.lds2);
+    g1 = std::max(8, std::min(c1, g1));
+    g2 = std::max(8, std::min(c2, g2));
     g1 = (g1 + 7) / 8 * 8;
     g2 = (g2 + 7) / 8 * 8;
-  } else {
-    g1 = ((P.k1_tasks + 7) / 8) * 8;
-    g2 = ((P.k2_tasks + 7) / 8) * 8;
   }
 }
 
@@ -441,8 +659,8 @@ hipError_t get_event(fftb_plan_s* P, hipEvent_t* e) {
 // Enqueue one direction: inverse = column kernel then plane kernel; forward =
 // plane kernel then column kernel. Persistent kernels first reset their work
 // counters with a kernel (graph-safe, no memset node).
-hipError_t enqueue(fftb_plan_s* P, const KArgs& a, bool inverse, int g1, int g2, hipStream_t st,
-                   bool profile) {
+hipError_t enqueue(fftb_plan_s* P, const KArgs& a, const DirCfg& D, bool inverse, int g1, int g2,
+                   hipStream_t st, bool profile) {
   const bool fp64 = P->dtype == FFTB_C128;
   hipError_t e = hipSuccess;
   if (a.persistent) {
@@ -459,8 +677,15 @@ hipError_t enqueue(fftb_plan_s* P, const KArgs& a, bool inverse, int g1, int g2,
       if ((e = get_event(P, &eb)) != hipSuccess) return e;
       if ((e = hipEventRecord(ea, st)) != hipSuccess) return e;
     }
-    e = launch_kernel(which, a, inverse, fp64, which == 1 ? g1 : g2, P->tun.threads,
-                      which == 1 ? P->lds1 : P->lds2, st);
+    const bool reg = which == 1 ? D.reg1 : D.reg2;
+    if (reg) {
+      e = launch_reg(which, a, inverse, fp64, which == 1 ? D.e1 : D.e2, which == 1 ? D.h1 : D.h2,
+                     which == 1 ? g1 : g2, which == 1 ? std::min(D.threads, 256) : D.threads,
+                     which == 1 ? 0 : D.lds2, st);
+    } else {
+      e = launch_kernel(which, a, inverse, fp64, which == 1 ? g1 : g2, D.threads,
+                        which == 1 ? D.lds1 : D.lds2, st);
+    }
     if (e != hipSuccess) return e;
     if (profile) {
       if ((e = hipEventRecord(eb, st)) != hipSuccess) return e;
@@ -475,9 +700,10 @@ fftb_status run(fftb_plan_s* P, const void* in, void* out, void* stream, bool in
   if (!P->device) return fail(FFTB_ERR_INVALID, "plan was created host-only");
   if (!in || !out) return fail(FFTB_ERR_INVALID, "null data pointer");
   hipStream_t st = static_cast<hipStream_t>(stream);
+  const DirCfg& D = P->dir[inverse ? 0 : 1];
   int g1, g2;
-  grids(*P, g1, g2);
-  KArgs a = make_args(*P, in, out, inverse);
+  grids(*P, D, g1, g2);
+  KArgs a = make_args(*P, D, in, out, inverse);
   if (P->flags & FFTB_PLAN_GRAPH) {
     auto& gc = P->gc[inverse ? 0 : 1];
     if (!gc.exec || gc.in != in || gc.out != out) {
@@ -489,7 +715,7 @@ fftb_status run(fftb_plan_s* P, const void* in, void* out, void* stream, bool in
       }
       hipError_t e = hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal);
       if (e != hipSuccess) return fail(FFTB_ERR_HIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
-      hipError_t el = enqueue(P, a, inverse, g1, g2, P->cap_stream, false);
+      hipError_t el = enqueue(P, a, D, inverse, g1, g2, P->cap_stream, false);
       e = hipStreamEndCapture(P->cap_stream, &gc.graph);
       if (el != hipSuccess) return fail(FFTB_ERR_HIP, std::string("launch during capture: ") + hipGetErrorString(el));
       if (e != hipSuccess) return fail(FFTB_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
@@ -502,8 +728,212 @@ fftb_status run(fftb_plan_s* P, const void* in, void* out, void* stream, bool in
     if (e != hipSuccess) return fail(FFTB_ERR_HIP, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
     return FFTB_OK;
   }
-  hipError_t e = enqueue(P, a, inverse, g1, g2, st, P->profiling);
+  hipError_t e = enqueue(P, a, D, inverse, g1, g2, st, P->profiling);
   if (e != hipSuccess) return fail(FFTB_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+  return FFTB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner: time candidate tilings of each direction on scratch buffers of
+// the plan's real size (warm-up + 3 timed executions with HIP events, never
+// inside a graph capture) and keep the fastest per direction. Results are
+// cached per input (FNV-1a hash of dims, dtype, persistent flag, the spheres'
+// sizes and maps) in the file named by FFTB_TUNE_CACHE, if set.
+
+uint64_t plan_key(const int32_t dims[3], const fftb_sphere* spheres, int nsph, fftb_dtype dt,
+                  uint32_t flags) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&h](const void* p, size_t n) {
+    const unsigned char* c = static_cast<const unsigned char*>(p);
+    for (size_t i = 0; i < n; ++i) {
+      h ^= c[i];
+      h *= 1099511628211ull;
+    }
+  };
+  mix(dims, 3 * sizeof(int32_t));
+  const int32_t d = dt;
+  mix(&d, sizeof d);
+  const uint32_t f = flags & (FFTB_PLAN_BATCHED | FFTB_PLAN_MFMA);
+  mix(&f, sizeof f);
+  for (int s = 0; s < nsph; ++s) {
+    mix(&spheres[s].n_coeffs, sizeof(int64_t));
+    mix(&spheres[s].nbands, sizeof(int32_t));
+    mix(spheres[s].map, sizeof(int32_t) * static_cast<size_t>(spheres[s].n_coeffs));
+  }
+  return h;
+}
+
+constexpr int kTuneInts = 16;
+
+void tuning_to_ints(const fftb_tuning& t, int32_t* v) {
+  std::memcpy(v, &t.inv, 8 * sizeof(int32_t));
+  std::memcpy(v + 8, &t.fwd, 8 * sizeof(int32_t));
+}
+void ints_to_tuning(const int32_t* v, fftb_tuning& t) {
+  std::memcpy(&t.inv, v, 8 * sizeof(int32_t));
+  std::memcpy(&t.fwd, v + 8, 8 * sizeof(int32_t));
+}
+
+bool cache_lookup(uint64_t key, fftb_tuning& t) {
+  const char* path = std::getenv("FFTB_TUNE_CACHE");
+  if (!path || !*path) return false;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  char tag[32];
+  unsigned long long k;
+  bool found = false;
+  while (std::fscanf(f, "%31s %llx", tag, &k) == 2) {
+    int32_t v[kTuneInts];
+    bool ok = true;
+    for (int i = 0; i < kTuneInts && ok; ++i) ok = std::fscanf(f, "%d", &v[i]) == 1;
+    if (!ok) break;
+    if (std::strcmp(tag, "fftb-tune-v1") == 0 && k == key) {
+      ints_to_tuning(v, t);
+      found = true;
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+
+void cache_store(uint64_t key, const fftb_tuning& t) {
+  const char* path = std::getenv("FFTB_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  int32_t v[kTuneInts];
+  tuning_to_ints(t, v);
+  std::fprintf(f, "fftb-tune-v1 %llx", static_cast<unsigned long long>(key));
+  for (int i = 0; i < kTuneInts; ++i) std::fprintf(f, " %d", v[i]);
+  std::fprintf(f, "\n");
+  std::fclose(f);
+}
+
+// Candidate tilings of one direction around the library defaults.
+std::vector<fftb_dir_tuning> candidates(const fftb_plan_s& P, bool inverse, const fftb_dir_tuning& base) {
+  std::vector<fftb_dir_tuning> out;
+  const bool fp64 = P.dtype == FFTB_C128;
+  const int bc0 = default_bc(P, fp64 ? 8 : 16);
+  std::vector<int> bcs = {bc0};
+  if (bc0 / 2 >= 1) bcs.push_back(bc0 / 2);
+  if (inverse && bc0 * 2 <= default_bc(P, 64)) bcs.push_back(bc0 * 2);
+  std::vector<int> classes = {0};
+  for (int m : {16, 8})
+    if (P.ny % m == 0) classes.push_back(P.ny / m);
+  for (int bc : bcs) {
+    for (int n1 : classes) {
+      for (int threads : {256, 512}) {
+        if (inverse) {
+          fftb_dir_tuning t = base;
+          t.band_chunk = bc;
+          t.y_classes = n1;
+          t.threads = threads;
+          t.path = 0;
+          out.push_back(t);
+        } else {
+          for (int acc : {1, 2}) {
+            for (int extra : {0, 1}) {
+              if (acc == 2 && extra) continue;
+              fftb_dir_tuning t = base;
+              t.band_chunk = bc;
+              t.y_classes = n1;
+              t.threads = threads;
+              t.path = 0;
+              t.acc = acc;
+              t.splits = extra ? -1 : 0;  // -1: one more split than the smallest that fits
+              out.push_back(t);
+            }
+          }
+        }
+      }
+    }
+    fftb_dir_tuning g = base;  // LDS-stage kernels
+    g.band_chunk = bc;
+    g.path = 1;
+    out.push_back(g);
+  }
+  return out;
+}
+
+fftb_status autotune(fftb_plan_s& P, const int32_t dims[3], const fftb_sphere* spheres, int nsph,
+                     fftb_dtype dtype, uint32_t flags, fftb_tuning& t, hipStream_t st) {
+  const uint64_t key = plan_key(dims, spheres, nsph, dtype, flags);
+  if (cache_lookup(key, t)) {
+    P.autotuned = 2;
+    return FFTB_OK;
+  }
+  const int es = es_of(dtype);
+  void *sin = nullptr, *sout = nullptr, *grid = nullptr;
+  if (hipMalloc(&sin, P.sphere_elems * es) != hipSuccess ||
+      hipMalloc(&sout, P.sphere_elems * es) != hipSuccess ||
+      hipMalloc(&grid, P.grid_elems * es) != hipSuccess) {
+    (void)hipGetLastError();
+    if (sin) (void)hipFree(sin);
+    if (sout) (void)hipFree(sout);
+    return FFTB_OK;  // not enough memory to tune: keep the defaults
+  }
+  (void)hipMemsetAsync(sin, 0, P.sphere_elems * es, st);
+  (void)hipMemsetAsync(grid, 0, P.grid_elems * es, st);
+  std::vector<fftb_dir_tuning> ci = candidates(P, true, t.inv);
+  std::vector<fftb_dir_tuning> cf = candidates(P, false, t.fwd);
+  const size_t n = std::max(ci.size(), cf.size());
+  double best[2] = {1e30, 1e30};
+  fftb_dir_tuning pick[2] = {t.inv, t.fwd};
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  const std::string saved_err = g_last_error;
+  for (size_t i = 0; i < n; ++i) {
+    fftb_tuning c = t;
+    c.inv = ci[std::min(i, ci.size() - 1)];
+    c.fwd = cf[std::min(i, cf.size() - 1)];
+    int extra_split = 0;
+    if (c.fwd.splits < 0) {
+      c.fwd.splits = 0;
+      extra_split = 1;
+    }
+    fftb_plan sub = nullptr;
+    const uint32_t sflags = flags & ~(FFTB_PLAN_AUTOTUNE | FFTB_PLAN_GRAPH);
+    if (extra_split) {
+      // find the smallest split count, then ask for one more
+      fftb_plan probe = nullptr;
+      if (fftb_plan_create(&probe, dims, spheres, nsph, dtype, sflags | FFTB_PLAN_HOST_ONLY, &c,
+                           nullptr) != FFTB_OK)
+        continue;
+      c.fwd.splits = std::min(8, probe->dir[1].nsplit + 1);
+      fftb_plan_destroy(probe);
+    }
+    if (fftb_plan_create(&sub, dims, spheres, nsph, dtype, sflags, &c, st) != FFTB_OK) continue;
+    for (int d = 0; d < 2; ++d) {
+      const bool inv = d == 0;
+      const void* in = inv ? sin : grid;
+      void* out = inv ? grid : sout;
+      fftb_status ok = run(sub, in, out, st, inv);
+      if (ok == FFTB_OK && hipEventRecord(e0, st) == hipSuccess) {
+        for (int r = 0; r < 3 && ok == FFTB_OK; ++r) ok = run(sub, in, out, st, inv);
+        float ms = 0.f;
+        if (ok == FFTB_OK && hipEventRecord(e1, st) == hipSuccess &&
+            hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess &&
+            ms < best[d]) {
+          best[d] = ms;
+          pick[d] = inv ? c.inv : c.fwd;
+        }
+      }
+    }
+    fftb_plan_destroy(sub);
+  }
+  (void)hipStreamSynchronize(st);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(sin);
+  (void)hipFree(sout);
+  (void)hipFree(grid);
+  (void)hipGetLastError();
+  g_last_error = saved_err;
+  if (best[0] < 1e30) t.inv = pick[0];
+  if (best[1] < 1e30) t.fwd = pick[1];
+  P.autotuned = 1;
+  cache_store(key, t);
   return FFTB_OK;
 }
 
@@ -554,11 +984,32 @@ fftb_status fftb_plan_create(fftb_plan* out, const int32_t dims[3], const fftb_s
       P->sphere_elems += P->sph[s].ns * P->sph[s].nb;
       P->grid_elems += N * P->sph[s].nb;
     }
-    fftb_status st = choose_tiling(*P, tuning);
-    if (st != FFTB_OK) return st;
-    build_descs(*P);
+    fftb_tuning t = {};
+    if (tuning) t = *tuning;
+    if ((flags & FFTB_PLAN_AUTOTUNE) && !(flags & FFTB_PLAN_HOST_ONLY)) {
+      fftb_status st = autotune(*P, dims, spheres, nspheres, dtype, flags, t,
+                                static_cast<hipStream_t>(stream));
+      if (st != FFTB_OK) return st;
+    }
+    for (int d = 0; d < 2; ++d) {
+      fftb_status st = choose_dir(*P, d, d == 0 ? t.inv : t.fwd);
+      if (st != FFTB_OK) return st;
+      build_descs(*P, P->dir[d]);
+    }
+    for (int d = 0; d < 2; ++d) {
+      const DirCfg& D = P->dir[d];
+      fftb_dir_tuning& o = d == 0 ? P->tun.inv : P->tun.fwd;
+      o.band_chunk = D.bc;
+      o.y_classes = D.n1;
+      o.x_rows = D.lx;
+      o.col_tile = D.lc;
+      o.threads = D.threads;
+      o.path = (D.reg1 && D.reg2) ? 2 : (D.reg1 || D.reg2) ? 0 : 1;
+      o.acc = d == 0 ? 0 : (D.reg2 && D.acc_lds) ? 1 : 2;
+      o.splits = D.nsplit;
+    }
     if (!(flags & FFTB_PLAN_HOST_ONLY)) {
-      st = device_setup(*P, static_cast<hipStream_t>(stream));
+      fftb_status st = device_setup(*P, static_cast<hipStream_t>(stream));
       if (st != FFTB_OK) return st;
     }
     *out = P.release();
@@ -603,9 +1054,10 @@ fftb_status fftb_plan_get_info(fftb_plan P, fftb_plan_info* info) {
   info->max_slab = P->max_nslab;
   info->workspace_bytes = static_cast<int64_t>(P->dev_bytes);
   for (int s = 0; s < P->ax.nst && s < 8; ++s) info->radix_x[s] = P->ax.R[s];
-  for (int s = 0; s < P->ay.nst && s < 8; ++s) info->radix_y[s] = P->ay.R[s];
+  for (int s = 0; s < P->dir[0].ay.nst && s < 8; ++s) info->radix_y[s] = P->dir[0].ay.R[s];
   for (int s = 0; s < P->az.nst && s < 8; ++s) info->radix_z[s] = P->az.R[s];
   info->tuning = P->tun;
+  info->autotuned = P->autotuned;
   return FFTB_OK;
 }
 

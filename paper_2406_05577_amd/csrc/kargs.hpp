@@ -31,6 +31,8 @@ struct SphereDesc {
   int32_t nchunk;      // ceil(nb / band_chunk)
   int32_t k1_start, k1_end;  // task range of the column kernel
   int32_t k2_start, k2_end;  // task range of the plane kernel
+  int32_t slab_off;    // nslab+1 table: first column of each occupied slab
+  int32_t split_off;   // nsplit+1 table: first slab of each forward column split
 };
 
 struct KArgs {
@@ -43,6 +45,10 @@ struct KArgs {
   int k1_tasks, k2_tasks;
   int persistent;
   int lds_P, lds_X0, lds_X1;  // element offsets of LDS regions (S starts at 0)
+  int lds_acc;       // element offset of the forward column accumulators
+  int acc_lds;       // forward plane kernel accumulates columns in LDS
+  int sx;            // element stride between slab lines of the class slab
+  int nsplit;        // forward plane tasks per (plane, chunk): slab ranges with their columns
   AxisDev ax, ay, az;
   const SphereDesc* sph;
   const int32_t* gidx;
@@ -50,6 +56,8 @@ struct KArgs {
   const int32_t* col_xi;
   const int32_t* col_y;
   const int32_t* xinv;
+  const int32_t* slabstart;
+  const int32_t* splits;
   const void* twx;      // forward-sign twiddles (double pairs, or FP32 hi)
   const void* twy;
   const void* twz;
@@ -58,6 +66,10 @@ struct KArgs {
   const void* twy_lo;
   const void* twz_lo;
   const void* twf_lo;
+  const void* rootx;    // exp(-2*pi*i*j/nx), j < nx (register path)
+  const void* rootx_lo;
+  const void* rootz;    // exp(-2*pi*i*j/nz), j < nz
+  const void* rootz_lo;
   const void* in;
   void* out;
   void* col;            // column scratch

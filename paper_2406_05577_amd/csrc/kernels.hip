@@ -16,250 +16,9 @@
 // access is bank-linear.
 #include <hip/hip_runtime.h>
 
-#include <type_traits>
-#include <utility>
-
-#include "kargs.hpp"
+#include "device_common.hpp"
 
 namespace fftb {
-
-constexpr int kMaxRadixDev = 16;
-
-template <typename T>
-struct alignas(2 * sizeof(T)) cpx {
-  T re, im;
-};
-
-template <typename T>
-__device__ __forceinline__ cpx<T> cadd(cpx<T> a, cpx<T> b) { return {a.re + b.re, a.im + b.im}; }
-template <typename T>
-__device__ __forceinline__ cpx<T> csub(cpx<T> a, cpx<T> b) { return {a.re - b.re, a.im - b.im}; }
-template <typename T>
-__device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b) {
-  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
-}
-template <typename T>
-__device__ __forceinline__ cpx<T> cscale(cpx<T> a, T s) { return {a.re * s, a.im * s}; }
-// multiply by S*i
-template <int S, typename T>
-__device__ __forceinline__ cpx<T> mul_si(cpx<T> a) {
-  if constexpr (S > 0) return {-a.im, a.re};
-  else return {a.im, -a.re};
-}
-
-// ---------------------------------------------------------------------------
-// Compile-time roots of unity for the in-register codelets: cos and sin of
-// 2*pi*j/R, reduced exactly in integers to the first octant, then a Taylor
-// series (|x| <= pi/4, 14 terms).
-constexpr double kHalfPi = 1.57079632679489661923132169163975144;
-
-constexpr double taylor_sin(double x) {
-  double x2 = x * x, term = x, sum = x;
-  for (int k = 1; k < 14; ++k) {
-    term *= -x2 / ((2.0 * k) * (2.0 * k + 1.0));
-    sum += term;
-  }
-  return sum;
-}
-constexpr double taylor_cos(double x) {
-  double x2 = x * x, term = 1.0, sum = 1.0;
-  for (int k = 1; k < 14; ++k) {
-    term *= -x2 / ((2.0 * k - 1.0) * (2.0 * k));
-    sum += term;
-  }
-  return sum;
-}
-// first-quadrant angle (pi/2) * r / R, 0 <= r < R
-constexpr double q_sin(int r, int R) {
-  return (2 * r <= R) ? taylor_sin(kHalfPi * r / R) : taylor_cos(kHalfPi * (R - r) / R);
-}
-constexpr double q_cos(int r, int R) {
-  return (2 * r <= R) ? taylor_cos(kHalfPi * r / R) : taylor_sin(kHalfPi * (R - r) / R);
-}
-// cos(2*pi*j/R), sin(2*pi*j/R)
-constexpr double kcos(int j, int R) {
-  j = ((j % R) + R) % R;
-  const int q = (4 * j) / R, r = 4 * j - q * R;
-  const double c = q_cos(r, R), s = q_sin(r, R);
-  return q == 0 ? c : q == 1 ? -s : q == 2 ? -c : s;
-}
-constexpr double ksin(int j, int R) {
-  j = ((j % R) + R) % R;
-  const int q = (4 * j) / R, r = 4 * j - q * R;
-  const double c = q_cos(r, R), s = q_sin(r, R);
-  return q == 0 ? s : q == 1 ? c : q == 2 ? -s : -c;
-}
-
-template <int B, int E, class F>
-__device__ __forceinline__ void static_for(F&& f) {
-  if constexpr (B < E) {
-    f(std::integral_constant<int, B>{});
-    static_for<B + 1, E>(f);
-  }
-}
-
-// x * exp(S*2*pi*i*J/R), with exact quarter turns folded at compile time.
-template <int J, int R, int S, typename T>
-__device__ __forceinline__ cpx<T> rot(cpx<T> x) {
-  constexpr int j = ((J % R) + R) % R;
-  if constexpr (j == 0) {
-    return x;
-  } else if constexpr (4 * j == R) {
-    return mul_si<S>(x);
-  } else if constexpr (2 * j == R) {
-    return {-x.re, -x.im};
-  } else if constexpr (4 * j == 3 * R) {
-    return mul_si<-S>(x);
-  } else {
-    constexpr T c = static_cast<T>(kcos(j, R));
-    constexpr T s = static_cast<T>(S * ksin(j, R));
-    return {x.re * c - x.im * s, x.re * s + x.im * c};
-  }
-}
-
-// ---------------------------------------------------------------------------
-// DFT codelets in registers, sign S (+1: exp(+...), -1: exp(-...)).
-template <int R, int S, typename T>
-__device__ __forceinline__ void dft(cpx<T>* v);
-
-template <int S, typename T>
-__device__ __forceinline__ void dft2(cpx<T>* v) {
-  const cpx<T> a = v[0], b = v[1];
-  v[0] = cadd(a, b);
-  v[1] = csub(a, b);
-}
-template <int S, typename T>
-__device__ __forceinline__ void dft3(cpx<T>* v) {
-  constexpr T h = static_cast<T>(0.866025403784438646763723170752936183);  // sin(2pi/3)
-  const cpx<T> a = v[0], b = v[1], c = v[2];
-  const cpx<T> t1 = cadd(b, c);
-  const cpx<T> t2 = {a.re - static_cast<T>(0.5) * t1.re, a.im - static_cast<T>(0.5) * t1.im};
-  const cpx<T> t3 = mul_si<S>(cscale(csub(b, c), h));
-  v[0] = cadd(a, t1);
-  v[1] = cadd(t2, t3);
-  v[2] = csub(t2, t3);
-}
-template <int S, typename T>
-__device__ __forceinline__ void dft4(cpx<T>* v) {
-  const cpx<T> a = v[0], b = v[1], c = v[2], d = v[3];
-  const cpx<T> s0 = cadd(a, c), s1 = csub(a, c), s2 = cadd(b, d);
-  const cpx<T> s3 = mul_si<S>(csub(b, d));
-  v[0] = cadd(s0, s2);
-  v[2] = csub(s0, s2);
-  v[1] = cadd(s1, s3);
-  v[3] = csub(s1, s3);
-}
-template <int S, typename T>
-__device__ __forceinline__ void dft5(cpx<T>* v) {
-  constexpr T c1 = static_cast<T>(kcos(1, 5)), c2 = static_cast<T>(kcos(2, 5));
-  constexpr T s1 = static_cast<T>(ksin(1, 5)), s2 = static_cast<T>(ksin(2, 5));
-  const cpx<T> a0 = v[0];
-  const cpx<T> t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
-  const cpx<T> t3 = csub(v[1], v[4]), t4 = csub(v[2], v[3]);
-  const cpx<T> r1 = {a0.re + c1 * t1.re + c2 * t2.re, a0.im + c1 * t1.im + c2 * t2.im};
-  const cpx<T> r2 = {a0.re + c2 * t1.re + c1 * t2.re, a0.im + c2 * t1.im + c1 * t2.im};
-  const cpx<T> i1 = mul_si<S>(cpx<T>{s1 * t3.re + s2 * t4.re, s1 * t3.im + s2 * t4.im});
-  const cpx<T> i2 = mul_si<S>(cpx<T>{s2 * t3.re - s1 * t4.re, s2 * t3.im - s1 * t4.im});
-  v[0] = cadd(a0, cadd(t1, t2));
-  v[1] = cadd(r1, i1);
-  v[4] = csub(r1, i1);
-  v[2] = cadd(r2, i2);
-  v[3] = csub(r2, i2);
-}
-
-// R = A*B: B sub-DFTs of length A over stride-B elements, twiddles, then A
-// sub-DFTs of length B (Section 2.1, Cooley-Tukey factorisation).
-template <int A, int B, int S, typename T>
-__device__ __forceinline__ void dft_ab(cpx<T>* v) {
-  constexpr int R = A * B;
-  cpx<T> u[R];
-  static_for<0, B>([&](auto bb) {
-    constexpr int b = decltype(bb)::value;
-    cpx<T> t[A];
-#pragma unroll
-    for (int a = 0; a < A; ++a) t[a] = v[b + B * a];
-    dft<A, S>(t);
-    static_for<0, A>([&](auto aa) {
-      constexpr int ap = decltype(aa)::value;
-      u[b * A + ap] = rot<b * ap, R, S>(t[ap]);
-    });
-  });
-#pragma unroll
-  for (int ap = 0; ap < A; ++ap) {
-    cpx<T> t[B];
-#pragma unroll
-    for (int b = 0; b < B; ++b) t[b] = u[b * A + ap];
-    dft<B, S>(t);
-#pragma unroll
-    for (int bp = 0; bp < B; ++bp) v[ap + A * bp] = t[bp];
-  }
-}
-
-template <int R, int S, typename T>
-__device__ __forceinline__ void dft(cpx<T>* v) {
-  if constexpr (R == 1) {
-  } else if constexpr (R == 2) {
-    dft2<S>(v);
-  } else if constexpr (R == 3) {
-    dft3<S>(v);
-  } else if constexpr (R == 4) {
-    dft4<S>(v);
-  } else if constexpr (R == 5) {
-    dft5<S>(v);
-  } else if constexpr (R == 6) {
-    dft_ab<3, 2, S>(v);
-  } else if constexpr (R == 8) {
-    dft_ab<4, 2, S>(v);
-  } else if constexpr (R == 9) {
-    dft_ab<3, 3, S>(v);
-  } else if constexpr (R == 10) {
-    dft_ab<5, 2, S>(v);
-  } else if constexpr (R == 12) {
-    dft_ab<4, 3, S>(v);
-  } else if constexpr (R == 15) {
-    dft_ab<5, 3, S>(v);
-  } else if constexpr (R == 16) {
-    dft_ab<4, 4, S>(v);
-  } else {
-    static_assert(R == 1, "unsupported radix");
-  }
-}
-
-template <int S, typename T>
-__device__ __forceinline__ void butterfly(int R, cpx<T>* v) {
-  switch (R) {
-    case 2: dft<2, S>(v); break;
-    case 3: dft<3, S>(v); break;
-    case 4: dft<4, S>(v); break;
-    case 5: dft<5, S>(v); break;
-    case 6: dft<6, S>(v); break;
-    case 8: dft<8, S>(v); break;
-    case 9: dft<9, S>(v); break;
-    case 10: dft<10, S>(v); break;
-    case 12: dft<12, S>(v); break;
-    case 15: dft<15, S>(v); break;
-    case 16: dft<16, S>(v); break;
-    default: break;
-  }
-}
-
-// Twiddle multiply with a forward-sign table entry; S > 0 conjugates it.
-// FP32 applies the compensated pair x*hi + x*lo.
-template <int S, typename T>
-__device__ __forceinline__ cpx<T> twmul(cpx<T> v, const cpx<T>* __restrict__ hi,
-                                         const cpx<T>* __restrict__ lo, int idx) {
-  cpx<T> w = hi[idx];
-  if constexpr (S > 0) w.im = -w.im;
-  if constexpr (std::is_same<T, float>::value) {
-    cpx<T> l = lo[idx];
-    if constexpr (S > 0) l.im = -l.im;
-    const cpx<T> a = cmul(v, w), b = cmul(v, l);
-    return cadd(a, b);
-  } else {
-    (void)lo;
-    return cmul(v, w);
-  }
-}
 
 // One Stockham stage over `nlines` lines of length n (radix R, sub-transform
 // length p): item (line, i, band) reads x[i + q*n/R], twiddles by

@@ -154,6 +154,8 @@ int build_sphere_tables(int nx, int ny, int nz, const int32_t* map, int64_t ns, 
       st.col_xi.push_back(st.xinv[x]);
     }
   st.ncol = ncol;
+  st.slabstart.assign(st.nslab + 1, ncol);
+  for (int c = ncol - 1; c >= 0; --c) st.slabstart[st.col_xi[c]] = c;
   st.colidx.assign(static_cast<size_t>(st.nslab) * ny, -1);
   for (int c = 0; c < ncol; ++c)
     st.colidx[static_cast<size_t>(st.col_xi[c]) * ny + st.col_y[c]] = c;

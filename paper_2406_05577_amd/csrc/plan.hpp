@@ -51,6 +51,7 @@ struct SphereTables {
   std::vector<int32_t> col_xi;         // slab index of each column
   std::vector<int32_t> xs;             // occupied x, ascending (nslab)
   std::vector<int32_t> xinv;           // nx entries: slab index or -1
+  std::vector<int32_t> slabstart;      // nslab+1 entries: first column of each slab
   std::vector<int32_t> colidx;         // nslab*ny: column index or -1
   std::vector<int32_t> gidx;           // ncol*nz: coefficient index or -1
   std::vector<int32_t> entry_col, entry_z;  // per coefficient

@@ -45,9 +45,37 @@ class Sphere_t(C.Structure):
                 ("kpt", C.c_double * 3), ("nbands", C.c_int32)]
 
 
+DIR_FIELDS = ["band_chunk", "y_classes", "x_rows", "col_tile", "threads", "path", "acc", "splits"]
+
+
+class DirTuning_t(C.Structure):
+    _fields_ = [(f, C.c_int32) for f in DIR_FIELDS]
+
+
 class Tuning_t(C.Structure):
-    _fields_ = [("band_chunk", C.c_int32), ("y_classes", C.c_int32), ("x_rows", C.c_int32),
-                ("col_tile", C.c_int32), ("threads", C.c_int32)]
+    _fields_ = [("inv", DirTuning_t), ("fwd", DirTuning_t)]
+
+
+def make_tuning(d: dict) -> Tuning_t:
+    """Flat dict -> per-direction struct: plain keys set both directions,
+    inv_<key> / fwd_<key> set one; acc and splits apply to the forward."""
+    t = Tuning_t()
+    for k, v in d.items():
+        if k.startswith("inv_") or k.startswith("fwd_"):
+            continue
+        if k not in DIR_FIELDS:
+            raise KeyError(f"unknown tuning key {k}")
+        if k not in ("acc", "splits"):
+            setattr(t.inv, k, int(v))
+        setattr(t.fwd, k, int(v))
+    for k, v in d.items():
+        for pre, part in (("inv_", t.inv), ("fwd_", t.fwd)):
+            if k.startswith(pre):
+                key = k[len(pre):]
+                if key not in DIR_FIELDS:
+                    raise KeyError(f"unknown tuning key {k}")
+                setattr(part, key, int(v))
+    return t
 
 
 class Info_t(C.Structure):
@@ -56,7 +84,8 @@ class Info_t(C.Structure):
                 ("grid_elems", C.c_int64), ("total_columns", C.c_int64),
                 ("max_columns", C.c_int32), ("max_slab", C.c_int32),
                 ("workspace_bytes", C.c_int64), ("radix_x", C.c_int32 * 8),
-                ("radix_y", C.c_int32 * 8), ("radix_z", C.c_int32 * 8), ("tuning", Tuning_t)]
+                ("radix_y", C.c_int32 * 8), ("radix_z", C.c_int32 * 8), ("tuning", Tuning_t),
+                ("autotuned", C.c_int32)]
 
 
 class Profile_t(C.Structure):
@@ -139,7 +168,9 @@ class Plan:
     kpts    -- optional list of k-points (metadata)
     dtype   -- "c128" or "c64"
     flags   -- PLAN_* bits
-    tuning  -- optional dict with keys band_chunk, y_classes, x_rows, col_tile, threads
+    tuning  -- optional dict of tiling knobs (band_chunk, y_classes, x_rows, col_tile,
+               threads, path, acc, splits); plain keys set both directions,
+               inv_<key> / fwd_<key> one of them
     """
 
     def __init__(self, dims: Sequence[int], maps, nbands, kpts=None, dtype: str = "c128",
@@ -160,9 +191,7 @@ class Plan:
             arr[i].kpt[:] = [float(v) for v in kpts[i]]
             arr[i].nbands = int(nbands[i])
         d = (C.c_int32 * 3)(*[int(v) for v in dims])
-        tun = None
-        if tuning:
-            tun = Tuning_t(**{k: int(v) for k, v in tuning.items()})
+        tun = make_tuning(tuning) if tuning else None
         self.dtype = dtype
         dt = FFTB_C128 if dtype == "c128" else FFTB_C64
         self._h = C.c_void_p()
@@ -181,7 +210,8 @@ class Plan:
         _check(lib().fftb_plan_get_info(self._h, C.byref(inf)))
         out = {f: getattr(inf, f) for f, _ in Info_t._fields_}
         out["dims"] = tuple(inf.dims)
-        out["tuning"] = {f: getattr(inf.tuning, f) for f, _ in Tuning_t._fields_}
+        out["tuning"] = {d: {f: getattr(getattr(inf.tuning, d), f) for f in DIR_FIELDS}
+                         for d in ("inv", "fwd")}
         for k in ("radix_x", "radix_y", "radix_z"):
             out[k] = [v for v in getattr(inf, k) if v]
         return out

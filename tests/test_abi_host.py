@@ -102,6 +102,10 @@ def test_validation_errors():
     _expect_status(pk.FFTB_ERR_INVALID, lambda: host_plan((4, 4, 4), [ok], tuning=dict(band_chunk=3)))
     _expect_status(pk.FFTB_ERR_INVALID, lambda: host_plan((4, 4, 4), [ok], tuning=dict(y_classes=3)))
     _expect_status(pk.FFTB_ERR_INVALID, lambda: host_plan((4, 4, 4), [ok], tuning=dict(threads=100)))
+    _expect_status(pk.FFTB_ERR_INVALID, lambda: host_plan((4, 4, 4), [ok], tuning=dict(fwd_splits=9)))
+    _expect_status(pk.FFTB_ERR_INVALID, lambda: host_plan((4, 4, 4), [ok], tuning=dict(acc=5)))
+    with pytest.raises(KeyError):
+        host_plan((4, 4, 4), [ok], tuning=dict(bogus=1))
 
 
 def test_null_pointers():
@@ -141,6 +145,7 @@ def test_tiling_fits_lds():
         w = synth.make_workload(name, nbands=1, nkpts=1)
         for dt in ("c128", "c64"):
             p = host_plan(w.dims, [w.spheres[0].lin], nb=synth.RECIPES[name]["nb"], dtype=dt)
-            t = p.info["tuning"]
-            assert w.dims[1] % t["y_classes"] == 0
-            assert t["band_chunk"] & (t["band_chunk"] - 1) == 0
+            for d in ("inv", "fwd"):
+                t = p.info["tuning"][d]
+                assert w.dims[1] % t["y_classes"] == 0
+                assert t["band_chunk"] & (t["band_chunk"] - 1) == 0

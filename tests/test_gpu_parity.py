@@ -26,13 +26,47 @@ CASES = [
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("path", [0, 1])
 @pytest.mark.parametrize("case", range(len(CASES)))
-def test_small_default(case, dtype):
+def test_small_default(case, path, dtype):
     dims, semi, kpts, nb, seed = CASES[case]
     w = synth.small_workload(dims, semi, kpts, nb, seed=seed, shuffle=(case % 2 == 1))
-    e = check_workload(w, dtype)
-    print(case, dtype, e)
+    e = check_workload(w, dtype, tuning=dict(path=path) if path else None)
+    print(case, path, dtype, e)
     assert max(e) <= TOL[dtype], e
+
+
+# grids whose x and z lengths have register-line shapes (32, 96, 128, 144, 180)
+REG_CASES = [
+    ((32, 32, 32), (8, 8, 8), [(0.0, 0.0, 0.0)], 5, 11),
+    ((96, 96, 96), (24, 24, 24), [(0.21, -0.33, 0.1), (-0.4, 0.05, 0.45)], 3, 12),
+    ((128, 128, 128), (32, 32, 32), [(0.0, 0.0, 0.0)], 2, 13),
+    ((144, 160, 180), (36, 40, 45), [(0.12, -0.3, 0.27)], 2, 14),
+]
+REG_TUNINGS = [None, dict(fwd_acc=2), dict(fwd_acc=1, fwd_band_chunk=2, fwd_splits=3),
+               dict(y_classes=4, fwd_y_classes=8), dict(band_chunk=2, col_tile=3, fwd_band_chunk=4),
+               dict(fwd_splits=5, threads=512)]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("ti", range(len(REG_TUNINGS)))
+@pytest.mark.parametrize("case", range(len(REG_CASES)))
+def test_register_path(case, ti, dtype):
+    dims, semi, kpts, nb, seed = REG_CASES[case]
+    t = REG_TUNINGS[ti]
+    if t and "y_classes" in t and dims[1] % 8:
+        pytest.skip("class count does not divide ny")
+    w = synth.small_workload(dims, semi, kpts, nb, seed=seed, shuffle=(case % 2 == 0))
+    tun = dict(t or {})
+    tun["path"] = 2
+    try:
+        e = check_workload(w, dtype, tuning=tun)
+    except Exception as ex:  # a tiling that does not fit is reported, not run
+        if "does not fit" in str(ex) or "no register-path" in str(ex):
+            pytest.skip(str(ex))
+        raise
+    print(dims, t, dtype, e)
+    assert max(e) <= TOL[dtype], (t, e)
 
 
 TUNINGS = [
@@ -53,8 +87,12 @@ def test_tunings(ti, dtype):
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("flags", [1, 4, 5])
-def test_batched_and_graph(flags, dtype):
-    dims, semi, kpts, nb, seed = CASES[5]
+@pytest.mark.parametrize("which", [0, 1])
+def test_batched_and_graph(which, flags, dtype):
+    if which == 0:
+        dims, semi, kpts, nb, seed = CASES[5]
+    else:
+        dims, semi, kpts, nb, seed = REG_CASES[1]
     w = synth.small_workload(dims, semi, kpts, nb, seed=seed)
     e = check_workload(w, dtype, flags=flags, reps=3)
     assert max(e) <= TOL[dtype], (flags, e)
@@ -81,3 +119,24 @@ def test_c3alt_full():
     e = check_workload(w, "c64")
     print("c3alt", e)
     assert max(e) <= 5e-6, e
+
+
+def test_autotune_and_cache(tmp_path, monkeypatch):
+    """FFTB_PLAN_AUTOTUNE times candidate tilings, keeps the fastest per
+    direction (parity must hold for the pick) and caches it: a second plan on
+    the same inputs reads the cache."""
+    from gpu_util import make_plan
+    monkeypatch.setenv("FFTB_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    dims, semi, kpts, nb, seed = REG_CASES[1]
+    w = synth.small_workload(dims, semi, kpts, nb, seed=seed)
+    for dtype in ("c128", "c64"):
+        p = make_plan(w, dtype=dtype, flags=2)
+        assert p.info["autotuned"] == 1
+        tun = p.info["tuning"]
+        p.close()
+        p2 = make_plan(w, dtype=dtype, flags=2)
+        assert p2.info["autotuned"] == 2 and p2.info["tuning"] == tun
+        p2.close()
+        e = check_workload(w, dtype, flags=2)
+        assert max(e) <= TOL[dtype], e
+    assert (tmp_path / "tune.txt").read_text().count("fftb-tune-v1") == 2
