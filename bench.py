@@ -102,6 +102,8 @@ def main():
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--flags", type=int, default=None, help="override plan flags")
     ap.add_argument("--tuning", default=None, help="JSON dict of tiling knobs")
+    ap.add_argument("--autotune", action="store_true",
+                    help="let the library time candidate tilings at plan creation (not timed)")
     ap.add_argument("--cpu-sample-bands", type=int, default=48)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
@@ -123,11 +125,15 @@ def main():
     recipe, dtype, flags = WORKLOADS[args.workload]
     if args.flags is not None:
         flags = args.flags
+    if args.autotune:
+        flags |= 2
     tuning = json.loads(args.tuning) if args.tuning else None
     torch.cuda.set_device(0)
     w = synth.make_workload(recipe, dtype=dtype)
+    t_plan = time.perf_counter()
     plan = Plan(w.dims, [s.lin for s in w.spheres], [s.nbands for s in w.spheres],
                 kpts=[s.kpt for s in w.spheres], dtype=dtype, flags=flags, tuning=tuning)
+    t_plan = time.perf_counter() - t_plan
     tdt = torch.complex128 if dtype == "c128" else torch.complex64
     sph = torch.from_numpy(w.sphere_concat()).to("cuda").to(tdt)
     back = torch.empty_like(sph)
@@ -206,7 +212,8 @@ def main():
                    "complex_dtype": "complex128" if dtype == "c128" else "complex64",
                    "dims": list(w.dims), "bands": nb_total, "spheres": len(w.spheres),
                    "coeffs": int(plan.info["total_coeffs"]), "plan_flags": flags,
-                   "tuning": plan.info["tuning"], "radix": {"x": plan.info["radix_x"],
+                   "tuning": plan.info["tuning"], "autotuned": plan.info["autotuned"],
+                   "plan_seconds": round(t_plan, 3), "radix": {"x": plan.info["radix_x"],
                    "y": plan.info["radix_y"], "z": plan.info["radix_z"]}},
         "step_roofline": {"algorithmic_bytes": b_min, "achieved_GBs": round(b_min / (ms / 1000) / 1e9, 1),
                           "frac": round(b_min / (ms / 1000) / 1e9 / HBM_PEAK_GBS, 4)},

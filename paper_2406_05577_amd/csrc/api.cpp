@@ -28,8 +28,9 @@ hipError_t launch_kernel(int which, const KArgs& a, bool inverse, bool fp64, int
                          size_t lds, hipStream_t st);
 bool reg_shape_supported(bool fp64, int E, int H);
 hipError_t launch_reg(int which, const KArgs& a, bool inverse, bool fp64, int E, int H, int grid,
-                      int threads, size_t lds, hipStream_t st);
-hipError_t prepare_reg(bool fp64, int E, int H, size_t lds);
+                      int threads, size_t lds, hipStream_t st, bool mfma);
+hipError_t prepare_reg(bool fp64, int E, int H, size_t lds, bool mfma);
+bool mfma_shape_supported(bool fp64, int E, int H);
 }  // namespace fftb
 
 using namespace fftb;
@@ -57,6 +58,7 @@ struct DevBuf {
 struct DirCfg {
   int bc = 8, n1 = 1, m = 1, lx = 1, lc = 1, threads = 256;
   bool reg1 = false, reg2 = false;  // register path for the column / plane kernel
+  bool mf1 = false, mf2 = false;    // DFT_16 stages on the matrix cores
   int e1 = 0, h1 = 0, e2 = 0, h2 = 0;
   bool class_par = false;           // plane tasks include the y class
   bool acc_lds = false;             // forward accumulators in LDS
@@ -318,8 +320,9 @@ fftb_status choose_dir(fftb_plan_s& P, int d, const fftb_dir_tuning& t) {
             const size_t bytes = (static_cast<size_t>(max_sl) * sx +
                                   (acc ? static_cast<size_t>(max_cl) * b : 0)) * es;
             if (bytes > kLdsMax) continue;
-            const double cost = eff * (1.0 + 0.12 * (Q - 1)) * (bytes > kLdsMax / 2 ? 1.15 : 1.0) *
-                                (acc ? 1.0 : 4.0);
+            // each class costs a pass over the split's accumulators and two barriers
+            const double cost = eff * (1.0 + 0.12 * (Q - 1)) * (1.0 + 0.03 * c) *
+                                (bytes > kLdsMax / 2 ? 1.15 : 1.0) * (acc ? 1.0 : 4.0);
             if (cost < best) {
               best = cost;
               D.reg2 = true;
@@ -353,6 +356,13 @@ fftb_status choose_dir(fftb_plan_s& P, int d, const fftb_dir_tuning& t) {
     return fail(FFTB_ERR_UNSUPPORTED, "x length has no register-path shape");
   }
   if (t.path == 2 && !D.reg1) return fail(FFTB_ERR_UNSUPPORTED, "z length has no register-path shape");
+  if (P.flags & FFTB_PLAN_MFMA) {
+    if (fp64) return fail(FFTB_ERR_UNSUPPORTED, "matrix-core DFT_16 stages are FP32 only");
+    D.mf1 = D.reg1 && mfma_shape_supported(fp64, D.e1, D.h1);
+    D.mf2 = D.reg2 && mfma_shape_supported(fp64, D.e2, D.h2);
+    if (!D.mf1 && !D.mf2)
+      return fail(FFTB_ERR_UNSUPPORTED, "no in-lane DFT_16 stage for the matrix cores in this plan");
+  }
   if (D.reg2) return FFTB_OK;
   // ---- plane kernel, LDS-stage path
   int lx = t.x_rows;
@@ -564,7 +574,7 @@ fftb_status device_setup(fftb_plan_s& P, hipStream_t st) {
     return fail(FFTB_ERR_HIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
   for (auto& D : P.dir) {
     if (!D.reg2) continue;
-    e = prepare_reg(fp64, D.e2, D.h2, r2);
+    e = prepare_reg(fp64, D.e2, D.h2, r2, D.mf2);
     if (e != hipSuccess)
       return fail(FFTB_ERR_HIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
   }
@@ -681,7 +691,7 @@ hipError_t enqueue(fftb_plan_s* P, const KArgs& a, const DirCfg& D, bool inverse
     if (reg) {
       e = launch_reg(which, a, inverse, fp64, which == 1 ? D.e1 : D.e2, which == 1 ? D.h1 : D.h2,
                      which == 1 ? g1 : g2, which == 1 ? std::min(D.threads, 256) : D.threads,
-                     which == 1 ? 0 : D.lds2, st);
+                     which == 1 ? 0 : D.lds2, st, which == 1 ? D.mf1 : D.mf2);
     } else {
       e = launch_kernel(which, a, inverse, fp64, which == 1 ? g1 : g2, D.threads,
                         which == 1 ? D.lds1 : D.lds2, st);

@@ -300,16 +300,77 @@ __device__ __forceinline__ cpx<T> root8(int j) {
   return {c[j & 7], static_cast<T>(S) * sn[j & 7]};
 }
 
+// ---------------------------------------------------------------------------
+// DFT_16 of 64 lines at once (one per lane of the wavefront) as a dense FP32
+// matrix product on the matrix cores: with v = (Re, Im) interleaved, the 16x16
+// complex DFT is the real 32x32 matrix M with M[2k][2s] = M[2k+1][2s+1] =
+// cos(2 pi k s/16), M[2k][2s+1] = -S sin(2 pi k s/16), M[2k+1][2s] = S sin(...).
+// v_mfma_f32_32x32x2f32 multiplies 32 rows of M by 2 input components of 32
+// lines per instruction, so each half of the wave's lines takes 16 steps. The
+// operand halves are paired with v_permlane32_swap before the products and the
+// result halves are paired back afterwards. Every lane of the wave must take
+// part (callers pad their loops to whole waves).
+typedef float mfma_f16v __attribute__((ext_vector_type(16)));
+
+__constant__ float c_cos16[16] = {
+    (float)kcos(0, 16), (float)kcos(1, 16), (float)kcos(2, 16), (float)kcos(3, 16),
+    (float)kcos(4, 16), (float)kcos(5, 16), (float)kcos(6, 16), (float)kcos(7, 16),
+    (float)kcos(8, 16), (float)kcos(9, 16), (float)kcos(10, 16), (float)kcos(11, 16),
+    (float)kcos(12, 16), (float)kcos(13, 16), (float)kcos(14, 16), (float)kcos(15, 16)};
+__constant__ float c_sin16[16] = {
+    (float)ksin(0, 16), (float)ksin(1, 16), (float)ksin(2, 16), (float)ksin(3, 16),
+    (float)ksin(4, 16), (float)ksin(5, 16), (float)ksin(6, 16), (float)ksin(7, 16),
+    (float)ksin(8, 16), (float)ksin(9, 16), (float)ksin(10, 16), (float)ksin(11, 16),
+    (float)ksin(12, 16), (float)ksin(13, 16), (float)ksin(14, 16), (float)ksin(15, 16)};
+
+__device__ __forceinline__ void pair_halves(float& x, float& y) {
+  // x <- (x lanes 0-31, y lanes 0-31), y <- (x lanes 32-63, y lanes 32-63)
+  const auto p = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+  x = __uint_as_float(p[0]);
+  y = __uint_as_float(p[1]);
+}
+
+template <int S>
+__device__ __forceinline__ void dft16_mfma(cpx<float>* v) {
+  const int lane = threadIdx.x & 63;
+  const int row = lane & 31;      // output component of M supplied by this lane
+  const int kk = lane >> 5;       // which of the two input components of a step
+  const int ko = row >> 1;        // output frequency
+  const bool im = row & 1;
+  mfma_f16v acc0 = {0}, acc1 = {0};
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    float b0 = v[s].re, b1 = v[s].im;
+    pair_halves(b0, b1);  // b0: operand for lines 0-31, b1: for lines 32-63
+    const int j = (ko * s) & 15;
+    const float c = c_cos16[j], sn = static_cast<float>(S) * c_sin16[j];
+    const float a = im ? (kk ? c : sn) : (kk ? -sn : c);
+    acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b0, acc0, 0, 0, 0);
+    acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b1, acc1, 0, 0, 0);
+  }
+  // acc[r] holds row 8*(r/4) + 4*(lane/32) + r%4 of column lane%32; pair the halves so
+  // that acc0 holds rows 8*(r/4) + r%4 and acc1 rows 8*(r/4) + 4 + r%4 of the lane's line
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    float x = acc0[r], y = acc1[r];
+    pair_halves(x, y);
+    const int o0 = 8 * (r >> 2) + (r & 3), o1 = o0 + 4;
+    if (o0 & 1) v[o0 >> 1].im = x; else v[o0 >> 1].re = x;
+    if (o1 & 1) v[o1 >> 1].im = y; else v[o1 >> 1].re = y;
+  }
+}
+
 // One transform line of length N = E*H spread over H adjacent lanes of a
 // wavefront (h = position of the lane in its group). On entry lane h holds
 // x[h + H*j] in v[j] (j < E); on exit it holds X[k + E*bitrev(h)] in v[k].
 // Cooley-Tukey with N = E*H (Section 2.1): DFT_E in registers, twiddles
 // w_N^{h*k} from the forward-sign root table of N, then DFT_H across the lanes
 // as log2(H) radix-2 rounds (partner h ^ H/2, then h ^ H/4, ...).
-template <int E, int H, int S, typename T>
+template <int E, int H, int S, typename T, bool MF = false>
 __device__ __forceinline__ void line_fft(cpx<T>* v, int h, const cpx<T>* __restrict__ rootN,
                                          const cpx<T>* __restrict__ rootN_lo) {
-  dft<E, S>(v);
+  if constexpr (MF && E == 16 && std::is_same<T, float>::value) dft16_mfma<S>(v);
+  else dft<E, S>(v);
   if constexpr (H > 1) {
     if (h > 0) {
 #pragma unroll

@@ -51,7 +51,7 @@ __device__ __forceinline__ int dynamic_task_r(unsigned int* counters, int total)
 }
 
 // ---------------------------------------------------------------------------
-template <int S, typename T, int E, int H>
+template <int S, typename T, int E, int H, bool MF>
 __device__ void k1r_task(const KArgs& a, int t) {
   constexpr int L = log2_const<H>();
   const int s = find_sphere_k1r(a, t);
@@ -70,9 +70,13 @@ __device__ void k1r_task(const KArgs& a, int t) {
   const cpx<T>* rootz = reinterpret_cast<const cpx<T>*>(a.rootz);
   const cpx<T>* rootz_lo = reinterpret_cast<const cpx<T>*>(a.rootz_lo);
   const int items = (nl << bcl) * H;
-  for (int it = threadIdx.x; it < items; it += blockDim.x) {
-    const int h = it % H;
-    const int rest = it / H;
+  // with the matrix-core codelet whole waves take part: pad to 64 lanes
+  const int iters = MF ? ((items + 63) & ~63) : items;
+  for (int it = threadIdx.x; it < iters; it += blockDim.x) {
+    const bool valid = !MF || it < items;
+    const int iv = valid ? it : 0;
+    const int h = iv % H;
+    const int rest = iv / H;
     const int bl = rest & bmask;
     const int c = c0 + (rest >> bcl);
     const int b = b0 + bl;
@@ -82,15 +86,17 @@ __device__ void k1r_task(const KArgs& a, int t) {
 #pragma unroll
       for (int j = 0; j < E; ++j) {
         const int g = gidx[c * nz + h + H * j];
-        v[j] = (g >= 0 && b < nb) ? in[static_cast<int64_t>(g) * nb + b] : cpx<T>{0, 0};
+        v[j] = (valid && g >= 0 && b < nb) ? in[static_cast<int64_t>(g) * nb + b] : cpx<T>{0, 0};
       }
     } else {
 #pragma unroll
       for (int j = 0; j < E; ++j)
-        v[j] = colbuf[((static_cast<int64_t>(h + H * j) * ncol + c) << bcl) + bl];
+        v[j] = valid ? colbuf[((static_cast<int64_t>(h + H * j) * ncol + c) << bcl) + bl]
+                     : cpx<T>{0, 0};
     }
-    line_fft<E, H, S>(v, h, rootz, rootz_lo);
+    line_fft<E, H, S, T, MF>(v, h, rootz, rootz_lo);
     const int q = bitrev_bits(h, L);
+    if (!valid) continue;
     if constexpr (S > 0) {
 #pragma unroll
       for (int k = 0; k < E; ++k)
@@ -108,7 +114,7 @@ __device__ void k1r_task(const KArgs& a, int t) {
 }
 
 // ---------------------------------------------------------------------------
-template <typename T, int E, int H>
+template <typename T, int E, int H, bool MF>
 __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S) {
   constexpr int L = log2_const<H>();
   const int s = find_sphere_k2r(a, t);
@@ -140,17 +146,18 @@ __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S) {
     for (int j = 0; j < m; ++j) line[j << bcl] = cpx<T>{0, 0};
     const int ce = sst[xi + 1];
     int c = sst[xi];
-    // batches of 8 columns: all loads in flight before the LDS updates
-    for (; c + 8 <= ce; c += 8) {
-      cpx<T> v[8];
-      int yy[8];
+    // batches of FB columns: all loads in flight before the LDS updates
+    constexpr int FB = sizeof(T) == 8 ? 8 : 16;
+    for (; c + FB <= ce; c += FB) {
+      cpx<T> v[FB];
+      int yy[FB];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < FB; ++u) {
         yy[u] = cy[c + u];
         v[u] = colp[((c + u) << bcl) + bl];
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < FB; ++u) {
         cpx<T>* p = line + ((yy[u] % m) << bcl);
         *p = cadd(*p, twmul<+1>(v[u], twf, twfl, (yy[u] * r) % ny));
       }
@@ -174,21 +181,24 @@ __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S) {
   // x-IFFT of the class's rows, written to the grid
   cpx<T>* __restrict__ gout = reinterpret_cast<cpx<T>*>(a.out) + d.grid_off;
   const int items = (m << bcl) * H;
-  for (int it = threadIdx.x; it < items; it += blockDim.x) {
-    const int h = it % H;
-    const int rest = it / H;
+  const int iters = MF ? ((items + 63) & ~63) : items;
+  for (int it = threadIdx.x; it < iters; it += blockDim.x) {
+    const bool valid = !MF || it < items;
+    const int iv = valid ? it : 0;
+    const int h = iv % H;
+    const int rest = iv / H;
     const int bl = rest & bmask, k2 = rest >> bcl;
     cpx<T> v[E];
 #pragma unroll
     for (int j = 0; j < E; ++j) {
       const int xi = xinv[h + H * j];
-      v[j] = xi >= 0 ? S[xi * sx + (k2 << bcl) + bl] : cpx<T>{0, 0};
+      v[j] = (valid && xi >= 0) ? S[xi * sx + (k2 << bcl) + bl] : cpx<T>{0, 0};
     }
-    line_fft<E, H, +1>(v, h, rootx, rootx_lo);
+    line_fft<E, H, +1, T, MF>(v, h, rootx, rootx_lo);
     const int q = bitrev_bits(h, L);
     const int y = r + n1 * k2;
     const int b = b0 + bl;
-    if (b < nb) {
+    if (valid && b < nb) {
       cpx<T>* row = gout + static_cast<int64_t>(z * ny + y) * nx * nb + b;
 #pragma unroll
       for (int k = 0; k < E; ++k) row[static_cast<int64_t>(k + E * q) * nb] = v[k];
@@ -197,7 +207,7 @@ __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S) {
 }
 
 // ---------------------------------------------------------------------------
-template <typename T, int E, int H>
+template <typename T, int E, int H, bool MF>
 __device__ void k2r_fwd_task(const KArgs& a, int t, cpx<T>* S) {
   constexpr int L = log2_const<H>();
   const int s = find_sphere_k2r(a, t);
@@ -214,6 +224,7 @@ __device__ void k2r_fwd_task(const KArgs& a, int t, cpx<T>* S) {
   const int nb = d.nb, ncol = d.ncol, nslab = d.nslab;
   const int32_t* __restrict__ xinv = a.xinv + d.xinv_off;
   const int32_t* __restrict__ cy = a.col_y + d.colmeta_off;
+  const int32_t* __restrict__ cxi = a.col_xi + d.colmeta_off;
   const int32_t* __restrict__ sst = a.slabstart + d.slab_off;
   cpx<T>* __restrict__ colp = reinterpret_cast<cpx<T>*>(a.col) + d.col_off +
                               (((static_cast<int64_t>(chunk) * a.nz + z) * ncol) << bcl);
@@ -230,9 +241,12 @@ __device__ void k2r_fwd_task(const KArgs& a, int t, cpx<T>* S) {
   for (int r = 0; r < n1; ++r) {
     // x-FFT of the class's rows, keeping the occupied x
     const int items = (m << bcl) * H;
-    for (int it = threadIdx.x; it < items; it += blockDim.x) {
-      const int h = it % H;
-      const int rest = it / H;
+    const int iters = MF ? ((items + 63) & ~63) : items;
+    for (int it = threadIdx.x; it < iters; it += blockDim.x) {
+      const bool valid = !MF || it < items;
+      const int iv = valid ? it : 0;
+      const int h = iv % H;
+      const int rest = iv / H;
       const int bl = rest & bmask, k2 = rest >> bcl;
       const int y = r + n1 * k2;
       const int b = b0 + bl;
@@ -240,9 +254,10 @@ __device__ void k2r_fwd_task(const KArgs& a, int t, cpx<T>* S) {
       const cpx<T>* row = gin + static_cast<int64_t>(z * ny + y) * nx * nb + b;
 #pragma unroll
       for (int j = 0; j < E; ++j)
-        v[j] = (b < nb) ? row[static_cast<int64_t>(h + H * j) * nb] : cpx<T>{0, 0};
-      line_fft<E, H, -1>(v, h, rootx, rootx_lo);
+        v[j] = (valid && b < nb) ? row[static_cast<int64_t>(h + H * j) * nb] : cpx<T>{0, 0};
+      line_fft<E, H, -1, T, MF>(v, h, rootx, rootx_lo);
       const int q = bitrev_bits(h, L);
+      if (!valid) continue;
 #pragma unroll
       for (int k = 0; k < E; ++k) {
         const int xi = xinv[k + E * q] - x_lo;
@@ -250,10 +265,10 @@ __device__ void k2r_fwd_task(const KArgs& a, int t, cpx<T>* S) {
       }
     }
     __syncthreads();
-    // y-FFT of length m per occupied x of the split, then the class's contribution to each column
+    // y-FFT of length m per occupied x of the split, in place
     const int nlines = (x_hi - x_lo) << bcl;
     for (int it = threadIdx.x; it < nlines; it += blockDim.x) {
-      const int bl = it & bmask, xl = it >> bcl, xi = x_lo + xl;
+      const int bl = it & bmask, xl = it >> bcl;
       cpx<T>* line = S + xl * sx + bl;
       cpx<T> u[kMaxRadixDev];
 #pragma unroll
@@ -263,20 +278,26 @@ __device__ void k2r_fwd_task(const KArgs& a, int t, cpx<T>* S) {
 #pragma unroll
       for (int j = 0; j < kMaxRadixDev; ++j)
         if (j < m) line[j << bcl] = u[j];
-      const int ce = sst[xi + 1];
-      for (int c = sst[xi]; c < ce; ++c) {
-        const int y = cy[c];
-        const cpx<T> val = twmul<-1>(line[(y % m) << bcl], twf, twfl, (y * r) % ny);
-        cpx<T>* g = colp + (c << bcl) + bl;
-        if (acc_lds) {
-          cpx<T>* p = acc + ((c - c_lo) << bcl) + bl;
-          if (n1 == 1) *g = val;
-          else if (r == 0) *p = val;
-          else if (r < n1 - 1) *p = cadd(*p, val);
-          else *g = cadd(*p, val);
-        } else {
-          *g = (r == 0) ? val : cadd(*g, val);
-        }
+    }
+    __syncthreads();
+    // the class's contribution w_ny^{-y*r} * Y[xi][y mod m] to each column of the
+    // split, one (column, band) item per thread
+    const int c_hi = sst[x_hi];
+    const int nitems = (c_hi - c_lo) << bcl;
+    for (int it = threadIdx.x; it < nitems; it += blockDim.x) {
+      const int bl = it & bmask, cl = it >> bcl, c = c_lo + cl;
+      const int y = cy[c];
+      const cpx<T> val =
+          twmul<-1>(S[(cxi[c] - x_lo) * sx + ((y % m) << bcl) + bl], twf, twfl, (y * r) % ny);
+      cpx<T>* g = colp + (c << bcl) + bl;
+      if (acc_lds) {
+        cpx<T>* p = acc + it;
+        if (n1 == 1) *g = val;
+        else if (r == 0) *p = val;
+        else if (r < n1 - 1) *p = cadd(*p, val);
+        else *g = cadd(*p, val);
+      } else {
+        *g = (r == 0) ? val : cadd(*g, val);
       }
     }
     __syncthreads();
@@ -284,11 +305,11 @@ __device__ void k2r_fwd_task(const KArgs& a, int t, cpx<T>* S) {
 }
 
 // ---------------------------------------------------------------------------
-template <int S, typename T, int E, int H>
+template <int S, typename T, int E, int H, bool MF>
 __global__ void __launch_bounds__(256) k1r_kernel(const KArgs a) {
   if (!a.persistent) {
     const int t = static_task_r(a.k1_tasks);
-    if (t >= 0) k1r_task<S, T, E, H>(a, t);
+    if (t >= 0) k1r_task<S, T, E, H, MF>(a, t);
     return;
   }
   __shared__ int sh_task;
@@ -298,19 +319,19 @@ __global__ void __launch_bounds__(256) k1r_kernel(const KArgs a) {
     const int t = sh_task;
     __syncthreads();
     if (t < 0) break;
-    k1r_task<S, T, E, H>(a, t);
+    k1r_task<S, T, E, H, MF>(a, t);
   }
 }
 
-template <int S, typename T, int E, int H>
+template <int S, typename T, int E, int H, bool MF>
 __global__ void __launch_bounds__(512) k2r_kernel(const KArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
   if (!a.persistent) {
     const int t = static_task_r(a.k2_tasks);
     if (t >= 0) {
-      if constexpr (S > 0) k2r_inv_task<T, E, H>(a, t, lds);
-      else k2r_fwd_task<T, E, H>(a, t, lds);
+      if constexpr (S > 0) k2r_inv_task<T, E, H, MF>(a, t, lds);
+      else k2r_fwd_task<T, E, H, MF>(a, t, lds);
     }
     return;
   }
@@ -321,8 +342,8 @@ __global__ void __launch_bounds__(512) k2r_kernel(const KArgs a) {
     const int t = sh_task;
     __syncthreads();
     if (t < 0) break;
-    if constexpr (S > 0) k2r_inv_task<T, E, H>(a, t, lds);
-    else k2r_fwd_task<T, E, H>(a, t, lds);
+    if constexpr (S > 0) k2r_inv_task<T, E, H, MF>(a, t, lds);
+    else k2r_fwd_task<T, E, H, MF>(a, t, lds);
     __syncthreads();
   }
 }
@@ -347,31 +368,41 @@ bool reg_shape_supported(bool fp64, int E, int H) {
   return false;
 }
 
-template <int S, typename T, int E, int H>
+template <int S, typename T, int E, int H, bool MF>
 static hipError_t launch_one(int which, const KArgs& a, int grid, int threads, size_t lds,
                              hipStream_t st) {
-  if (which == 1) hipLaunchKernelGGL((k1r_kernel<S, T, E, H>), dim3(grid), dim3(threads), 0, st, a);
-  else hipLaunchKernelGGL((k2r_kernel<S, T, E, H>), dim3(grid), dim3(threads), lds, st, a);
+  if (which == 1)
+    hipLaunchKernelGGL((k1r_kernel<S, T, E, H, MF>), dim3(grid), dim3(threads), 0, st, a);
+  else
+    hipLaunchKernelGGL((k2r_kernel<S, T, E, H, MF>), dim3(grid), dim3(threads), lds, st, a);
   return hipGetLastError();
 }
 
-template <int S, typename T, int E, int H>
+template <int S, typename T, int E, int H, bool MF>
 static hipError_t attr_one(size_t lds) {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(k2r_kernel<S, T, E, H>),
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(k2r_kernel<S, T, E, H, MF>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
+// the FP32 DFT_16 on the matrix cores is compiled for lines of 16 values per lane
+bool mfma_shape_supported(bool fp64, int E, int H) { return !fp64 && E == 16 && H == 8; }
+
 // which: 1 = column kernel (E, H of the z axis), 2 = plane kernel (E, H of x)
 hipError_t launch_reg(int which, const KArgs& a, bool inverse, bool fp64, int E, int H, int grid,
-                      int threads, size_t lds, hipStream_t st) {
-#define FFTB_L64(e, h)                                                                   \
-  if (E == e && H == h)                                                                  \
-    return inverse ? launch_one<+1, double, e, h>(which, a, grid, threads, lds, st)      \
-                   : launch_one<-1, double, e, h>(which, a, grid, threads, lds, st);
-#define FFTB_L32(e, h)                                                                   \
-  if (E == e && H == h)                                                                  \
-    return inverse ? launch_one<+1, float, e, h>(which, a, grid, threads, lds, st)       \
-                   : launch_one<-1, float, e, h>(which, a, grid, threads, lds, st);
+                      int threads, size_t lds, hipStream_t st, bool mfma) {
+  if (mfma) {
+    if (fp64 || E != 16 || H != 8) return hipErrorInvalidValue;
+    return inverse ? launch_one<+1, float, 16, 8, true>(which, a, grid, threads, lds, st)
+                   : launch_one<-1, float, 16, 8, true>(which, a, grid, threads, lds, st);
+  }
+#define FFTB_L64(e, h)                                                                     \
+  if (E == e && H == h)                                                                    \
+    return inverse ? launch_one<+1, double, e, h, false>(which, a, grid, threads, lds, st) \
+                   : launch_one<-1, double, e, h, false>(which, a, grid, threads, lds, st);
+#define FFTB_L32(e, h)                                                                     \
+  if (E == e && H == h)                                                                    \
+    return inverse ? launch_one<+1, float, e, h, false>(which, a, grid, threads, lds, st)  \
+                   : launch_one<-1, float, e, h, false>(which, a, grid, threads, lds, st);
   if (fp64) {
     FFTB_REG_SHAPES_F64(FFTB_L64)
   } else {
@@ -382,16 +413,21 @@ hipError_t launch_reg(int which, const KArgs& a, bool inverse, bool fp64, int E,
   return hipErrorInvalidValue;
 }
 
-hipError_t prepare_reg(bool fp64, int E, int H, size_t lds) {
-#define FFTB_A64(e, h)                                               \
-  if (E == e && H == h) {                                            \
-    hipError_t err = attr_one<+1, double, e, h>(lds);                \
-    return err != hipSuccess ? err : attr_one<-1, double, e, h>(lds); \
+hipError_t prepare_reg(bool fp64, int E, int H, size_t lds, bool mfma) {
+  if (mfma) {
+    if (fp64 || E != 16 || H != 8) return hipErrorInvalidValue;
+    hipError_t err = attr_one<+1, float, 16, 8, true>(lds);
+    return err != hipSuccess ? err : attr_one<-1, float, 16, 8, true>(lds);
   }
-#define FFTB_A32(e, h)                                              \
-  if (E == e && H == h) {                                           \
-    hipError_t err = attr_one<+1, float, e, h>(lds);                \
-    return err != hipSuccess ? err : attr_one<-1, float, e, h>(lds); \
+#define FFTB_A64(e, h)                                                      \
+  if (E == e && H == h) {                                                   \
+    hipError_t err = attr_one<+1, double, e, h, false>(lds);                \
+    return err != hipSuccess ? err : attr_one<-1, double, e, h, false>(lds); \
+  }
+#define FFTB_A32(e, h)                                                     \
+  if (E == e && H == h) {                                                  \
+    hipError_t err = attr_one<+1, float, e, h, false>(lds);                \
+    return err != hipSuccess ? err : attr_one<-1, float, e, h, false>(lds); \
   }
   if (fp64) {
     FFTB_REG_SHAPES_F64(FFTB_A64)

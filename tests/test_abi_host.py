@@ -149,3 +149,17 @@ def test_tiling_fits_lds():
                 t = p.info["tuning"][d]
                 assert w.dims[1] % t["y_classes"] == 0
                 assert t["band_chunk"] & (t["band_chunk"] - 1) == 0
+
+
+def test_mfma_flag_validation():
+    m, lin = synth.sphere_map((128, 16, 128), (20, 4, 20))
+    p = pk.Plan((128, 16, 128), [lin], 16, dtype="c64", flags=pk.PLAN_HOST_ONLY | pk.PLAN_MFMA)
+    assert p.info["flags"] & pk.PLAN_MFMA
+    # FP64 has no matrix-core DFT_16 stage; a plan without a 16-value lane has none either
+    _expect_status(pk.FFTB_ERR_UNSUPPORTED,
+                   lambda: pk.Plan((128, 16, 128), [lin], 16, dtype="c128",
+                                   flags=pk.PLAN_HOST_ONLY | pk.PLAN_MFMA))
+    m2, lin2 = synth.sphere_map((96, 16, 96), (20, 4, 20))
+    _expect_status(pk.FFTB_ERR_UNSUPPORTED,
+                   lambda: pk.Plan((96, 16, 96), [lin2], 16, dtype="c64",
+                                   flags=pk.PLAN_HOST_ONLY | pk.PLAN_MFMA))

@@ -140,3 +140,14 @@ def test_autotune_and_cache(tmp_path, monkeypatch):
         e = check_workload(w, dtype, flags=2)
         assert max(e) <= TOL[dtype], e
     assert (tmp_path / "tune.txt").read_text().count("fftb-tune-v1") == 2
+
+
+@pytest.mark.parametrize("flags", [16, 16 | 1 | 4])
+def test_mfma_radix16(flags):
+    """complex64 with the in-lane DFT_16 stages on the matrix cores (FP32
+    v_mfma_f32_32x32x2f32), against the FP64 oracle."""
+    dims, semi, kpts, nb, seed = REG_CASES[2]
+    w = synth.small_workload(dims, semi, kpts, 5, seed=seed, shuffle=True)
+    e = check_workload(w, "c64", flags=flags, reps=2)
+    print("mfma", flags, e)
+    assert max(e) <= TOL["c64"], e
