@@ -180,7 +180,8 @@ def main():
     kern = {}
     if profile:
         for k, (n, t) in prof.items():
-            kern[k] = {"launches": n, "avg_ms": (t / n) if n else None}
+            if n:
+                kern[k] = {"launches": n, "avg_ms": t / n}
         n_inv, t_inv = prof["plane_inverse"]
         n_fwd, t_fwd = prof["plane_forward"]
         if n_inv and n_fwd:

@@ -98,7 +98,10 @@ typedef struct {
   int32_t threads;      /* plane-kernel workgroup size: 64, 128, 256 or 512 */
   int32_t path;         /* 0 = choose, 1 = LDS-stage kernels, 2 = register-line kernels */
   int32_t acc;          /* forward only: 0 = choose, 1 = column accumulators in LDS (the plane's
-                           columns split over workgroups), 2 = accumulators in global memory */
+                           columns split over workgroups), 2 = accumulators in global memory,
+                           3 = one task per y class writing class partials that a combine
+                           kernel turns into columns (a length-n1 DFT over the classes;
+                           needs the register-line column kernel and one split) */
   int32_t splits;       /* forward only: column splits per (plane, chunk), 1..8 */
 } fftb_dir_tuning;
 
@@ -180,10 +183,11 @@ fftb_status fftb_plan_sphere_columns(fftb_plan plan, int32_t sphere, int32_t* co
 /* Per-kernel timing of execute calls, measured with HIP events recorded on
  * the execute stream around each kernel launch (not available for graph
  * replays). Index 0: column kernel, inverse; 1: plane kernel, inverse;
- * 2: plane kernel, forward; 3: column kernel, forward. */
+ * 2: plane kernel, forward; 3: column kernel, forward; 4: class combine,
+ * forward (plans whose forward plane kernel writes class partials). */
 typedef struct {
-  int64_t launches[4];
-  double total_ms[4];
+  int64_t launches[5];
+  double total_ms[5];
 } fftb_profile;
 
 /* Turn per-kernel event timing on (enable != 0) or off for later execute calls. */

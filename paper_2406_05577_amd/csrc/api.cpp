@@ -28,9 +28,11 @@ hipError_t launch_kernel(int which, const KArgs& a, bool inverse, bool fp64, int
                          size_t lds, hipStream_t st);
 bool reg_shape_supported(bool fp64, int E, int H);
 hipError_t launch_reg(int which, const KArgs& a, bool inverse, bool fp64, int E, int H, int grid,
-                      int threads, size_t lds, hipStream_t st, bool mfma);
+                      int threads, size_t lds, hipStream_t st, bool mfma, int fold_m);
 hipError_t prepare_reg(bool fp64, int E, int H, size_t lds, bool mfma);
 bool mfma_shape_supported(bool fp64, int E, int H);
+bool fold_m_supported(int H, int m);
+hipError_t launch_combine(const KArgs& a, bool fp64, int grid, int threads, hipStream_t st);
 }  // namespace fftb
 
 using namespace fftb;
@@ -62,6 +64,8 @@ struct DirCfg {
   int e1 = 0, h1 = 0, e2 = 0, h2 = 0;
   bool class_par = false;           // plane tasks include the y class
   bool acc_lds = false;             // forward accumulators in LDS
+  bool fwd_cls = false;             // forward class partials, combined by the column kernel
+  int fold_m = 0;                   // inverse: compile-time class length of the fold (0 = generic)
   int nsplit = 1;                   // forward plane tasks per (plane, chunk)
   std::vector<int32_t> splits;      // per sphere nsplit+1 slab boundaries
   int sx = 0;
@@ -69,7 +73,7 @@ struct DirCfg {
   int lds_P = 0, lds_X0 = 0, lds_X1 = 0, lds_acc = 0;
   AxisPlan ay;                      // y plan of length m
   std::vector<SphereDesc> desc;
-  int k1_tasks = 0, k2_tasks = 0;
+  int k1_tasks = 0, k2_tasks = 0, k3_tasks = 0;
   int64_t col_elems = 0;
   SphereDesc* d_desc = nullptr;
   int32_t* d_splits = nullptr;
@@ -96,7 +100,8 @@ struct fftb_plan_s {
   // device memory
   std::vector<DevBuf> bufs;
   int32_t *d_gidx = nullptr, *d_colidx = nullptr, *d_colxi = nullptr, *d_coly = nullptr,
-          *d_xinv = nullptr, *d_slabstart = nullptr;
+          *d_xinv = nullptr, *d_slabstart = nullptr, *d_slabruns = nullptr, *d_slaborder = nullptr;
+  bool two_runs = true;  // every slab of every sphere is at most two runs of y
   void *d_twx = nullptr, *d_twz = nullptr, *d_twf = nullptr;
   void *d_twx_lo = nullptr, *d_twz_lo = nullptr, *d_twf_lo = nullptr;
   void *d_rootx = nullptr, *d_rootx_lo = nullptr, *d_rootz = nullptr, *d_rootz_lo = nullptr;
@@ -119,8 +124,8 @@ struct fftb_plan_s {
   };
   std::vector<ProfRec> prof_pending;
   std::vector<hipEvent_t> ev_pool;
-  int64_t prof_launches[4] = {0, 0, 0, 0};
-  double prof_ms[4] = {0, 0, 0, 0};
+  int64_t prof_launches[5] = {0, 0, 0, 0, 0};
+  double prof_ms[5] = {0, 0, 0, 0, 0};
 
   ~fftb_plan_s() {
     for (auto& r : prof_pending) {
@@ -238,7 +243,7 @@ fftb_status choose_dir(fftb_plan_s& P, int d, const fftb_dir_tuning& t) {
     return fail(FFTB_ERR_INVALID, "threads must be 64, 128, 256 or 512");
   if (n1 != 0 && (n1 < 1 || P.ny % n1)) return fail(FFTB_ERR_INVALID, "y_classes must divide ny");
   if (t.path < 0 || t.path > 2) return fail(FFTB_ERR_INVALID, "path must be 0, 1 or 2");
-  if (t.acc < 0 || t.acc > 2) return fail(FFTB_ERR_INVALID, "acc must be 0, 1 or 2");
+  if (t.acc < 0 || t.acc > 3) return fail(FFTB_ERR_INVALID, "acc must be 0, 1, 2 or 3");
   if (t.splits < 0 || t.splits > 8) return fail(FFTB_ERR_INVALID, "splits must be in [1, 8]");
   if (t.col_tile < 0) return fail(FFTB_ERR_INVALID, "col_tile must be >= 1");
   if (t.x_rows < 0) return fail(FFTB_ERR_INVALID, "x_rows must be >= 1");
@@ -270,15 +275,18 @@ fftb_status choose_dir(fftb_plan_s& P, int d, const fftb_dir_tuning& t) {
   // ---- plane kernel, register path
   int e2 = 0, h2 = 0;
   D.reg2 = false;
-  if (t.path != 1 && reg_shape(P.nx, fp64, e2, h2)) {
-    if (inverse) {
-      // class-parallel tasks; the class slab must fit (aim for two workgroups per CU
-      // unless the class count is fixed)
-      const size_t cap = n1 ? kLdsMax : kLdsMax / 2;
+  // class-parallel tasks (plane, chunk, class): the class slab must fit (aim for
+  // two workgroups per CU unless the class count is fixed)
+  // want_fold_m: only class lengths with a compiled inverse fold; want_codelet:
+  // only class counts with a DFT codelet (the forward combine)
+  auto pick_classes = [&](bool want_fold_m, bool want_codelet) {
+    for (size_t cap : {n1 ? kLdsMax : kLdsMax / 2, kLdsMax}) {
       for (int c = 1; c <= P.ny; ++c) {
         if (P.ny % c || (n1 && c != n1)) continue;
         const int m = P.ny / c;
         if (!single_codelet(m)) continue;
+        if (want_fold_m && !fold_m_supported(h2, m)) continue;
+        if (want_codelet && !single_codelet(c)) continue;
         int sx, oa;
         const size_t b = plane_lds_reg(P, m, bc, false, sx, oa);
         if (b > cap) continue;
@@ -288,9 +296,29 @@ fftb_status choose_dir(fftb_plan_s& P, int d, const fftb_dir_tuning& t) {
         D.lds2 = b;
         D.sx = sx;
         D.class_par = true;
-        break;
+        return;
       }
-    } else {
+    }
+  };
+  D.fwd_cls = false;
+  D.fold_m = 0;
+  if (t.path != 1 && reg_shape(P.nx, fp64, e2, h2)) {
+    if (inverse) {
+      // prefer a class length with a compiled register fold
+      if (P.two_runs) pick_classes(true, false);
+      if (!D.reg2) pick_classes(false, false);
+      D.fold_m = D.reg2 && P.two_runs && fold_m_supported(h2, D.m) ? D.m : 0;
+    } else if ((t.acc == 0 || t.acc == 3) && t.splits <= 1 && D.reg1) {
+      // class partials combined by a separate kernel: no accumulators
+      pick_classes(false, true);
+      if (!D.reg2) pick_classes(false, false);
+      D.fwd_cls = D.reg2;
+      if (!D.reg2 && t.acc == 3)
+        return fail(FFTB_ERR_UNSUPPORTED, "no class slab fits in LDS");
+    } else if (t.acc == 3) {
+      return fail(FFTB_ERR_UNSUPPORTED, "class partials need the register column kernel and no splits");
+    }
+    if (!inverse && !D.reg2) {
       // forward: the plane's columns are split into nsplit slab ranges whose
       // accumulators (LDS) and class slab fit; each split redoes the x transform of
       // the class rows. Cost model: HBM segment efficiency x redundant x work x
@@ -429,8 +457,9 @@ void build_descs(fftb_plan_s& P, DirCfg& D) {
   D.desc.clear();
   D.splits.clear();
   int64_t soff = 0, goff = 0, coff = 0;
-  int32_t gi = 0, ci = 0, cm = 0, xo = 0, so = 0;
-  int k1 = 0, k2 = 0;
+  int32_t gi = 0, ci = 0, cm = 0, xo = 0, so = 0, sl = 0;
+  int k1 = 0, k2 = 0, k3 = 0;
+  int64_t zoff = 0;
   for (auto& s : P.sph) {
     SphereDesc d = {};
     d.sph_off = soff;
@@ -441,6 +470,7 @@ void build_descs(fftb_plan_s& P, DirCfg& D) {
     d.colmeta_off = cm;
     d.xinv_off = xo;
     d.slab_off = so;
+    d.sl_off = sl;
     d.ncol = s.ncol;
     d.nslab = s.nslab;
     d.nb = s.nb;
@@ -455,19 +485,28 @@ void build_descs(fftb_plan_s& P, DirCfg& D) {
     split_slabs(s, D.nsplit, cuts);
     D.splits.insert(D.splits.end(), cuts.begin(), cuts.end());
     d.k2_end = k2;
+    d.k3_start = k3;
+    if (D.fwd_cls) k3 += P.nz * d.nchunk;
+    d.k3_end = k3;
+    d.zp_off = zoff;  // relative to the end of the column region, fixed up below
     soff += s.ns * s.nb;
     goff += N * s.nb;
     coff += static_cast<int64_t>(d.nchunk) * bc * P.nz * s.ncol;
+    if (D.fwd_cls) zoff += static_cast<int64_t>(d.nchunk) * bc * P.nz * s.nslab * P.ny;
     gi += s.ncol * P.nz;
     ci += s.nslab * P.ny;
     cm += s.ncol;
     xo += P.nx;
     so += s.nslab + 1;
+    sl += s.nslab;
     D.desc.push_back(d);
   }
+  // the forward class partials follow the column region
+  for (auto& d : D.desc) d.zp_off += coff;
   D.k1_tasks = k1;
   D.k2_tasks = k2;
-  D.col_elems = coff;
+  D.k3_tasks = k3;
+  D.col_elems = coff + zoff;
 }
 
 fftb_status dev_alloc(fftb_plan_s& P, size_t bytes, void** out) {
@@ -520,8 +559,10 @@ fftb_status device_setup(fftb_plan_s& P, hipStream_t st) {
   if (e != hipSuccess)
     return fail(FFTB_ERR_HIP, std::string("hipGetDeviceProperties: ") + hipGetErrorString(e));
   P.num_cus = prop.multiProcessorCount;
-  std::vector<int32_t> gidx, colidx, colxi, coly, xinv, slabstart;
+  std::vector<int32_t> gidx, colidx, colxi, coly, xinv, slabstart, slabruns, slaborder;
   for (auto& s : P.sph) {
+    slabruns.insert(slabruns.end(), s.slab_runs.begin(), s.slab_runs.end());
+    slaborder.insert(slaborder.end(), s.slab_order.begin(), s.slab_order.end());
     gidx.insert(gidx.end(), s.gidx.begin(), s.gidx.end());
     colidx.insert(colidx.end(), s.colidx.begin(), s.colidx.end());
     colxi.insert(colxi.end(), s.col_xi.begin(), s.col_xi.end());
@@ -550,6 +591,10 @@ fftb_status device_setup(fftb_plan_s& P, hipStream_t st) {
   P.d_xinv = static_cast<int32_t*>(p);
   if ((s = upload(P, slabstart, &p, st)) != FFTB_OK) return s;
   P.d_slabstart = static_cast<int32_t*>(p);
+  if ((s = upload(P, slabruns, &p, st)) != FFTB_OK) return s;
+  P.d_slabruns = static_cast<int32_t*>(p);
+  if ((s = upload(P, slaborder, &p, st)) != FFTB_OK) return s;
+  P.d_slaborder = static_cast<int32_t*>(p);
   if ((s = upload_tw(P, axis_twiddles(P.ax), &P.d_twx, &P.d_twx_lo, st)) != FFTB_OK) return s;
   if ((s = upload_tw(P, axis_twiddles(P.az), &P.d_twz, &P.d_twz_lo, st)) != FFTB_OK) return s;
   if ((s = upload_tw(P, root_table(P.ny), &P.d_twf, &P.d_twf_lo, st)) != FFTB_OK) return s;
@@ -558,9 +603,9 @@ fftb_status device_setup(fftb_plan_s& P, hipStream_t st) {
   const int64_t col_elems = std::max(P.dir[0].col_elems, P.dir[1].col_elems);
   if ((s = dev_alloc(P, static_cast<size_t>(col_elems) * es_of(P.dtype), &P.d_col)) != FFTB_OK)
     return s;
-  if ((s = dev_alloc(P, 16 * sizeof(unsigned int), &p)) != FFTB_OK) return s;
+  if ((s = dev_alloc(P, 24 * sizeof(unsigned int), &p)) != FFTB_OK) return s;
   P.d_counters = static_cast<unsigned int*>(p);
-  e = hipMemsetAsync(P.d_counters, 0, 16 * sizeof(unsigned int), st);
+  e = hipMemsetAsync(P.d_counters, 0, 24 * sizeof(unsigned int), st);
   if (e != hipSuccess) return fail(FFTB_ERR_HIP, std::string("hipMemsetAsync: ") + hipGetErrorString(e));
   const bool fp64 = P.dtype == FFTB_C128;
   size_t g1 = 4, g2 = 4, r2 = 4;
@@ -599,6 +644,7 @@ KArgs make_args(const fftb_plan_s& P, const DirCfg& D, const void* in, void* out
   a.nsph = static_cast<int>(P.sph.size());
   a.k1_tasks = D.k1_tasks;
   a.k2_tasks = D.k2_tasks;
+  a.k3_tasks = D.k3_tasks;
   a.persistent = (P.flags & FFTB_PLAN_BATCHED) ? 1 : 0;
   a.lds_P = D.lds_P;
   a.lds_X0 = D.lds_X0;
@@ -607,6 +653,8 @@ KArgs make_args(const fftb_plan_s& P, const DirCfg& D, const void* in, void* out
   a.acc_lds = D.acc_lds ? 1 : 0;
   a.sx = D.sx;
   a.nsplit = D.nsplit;
+  a.fwd_cls = D.fwd_cls ? 1 : 0;
+  a.g2 = D.reg2 ? (D.class_par ? D.n1 : D.nsplit) : 1;
   a.splits = D.d_splits;
   fill_axis(P.ax, a.ax);
   fill_axis(D.ay, a.ay);
@@ -618,6 +666,8 @@ KArgs make_args(const fftb_plan_s& P, const DirCfg& D, const void* in, void* out
   a.col_y = P.d_coly;
   a.xinv = P.d_xinv;
   a.slabstart = P.d_slabstart;
+  a.slab_runs = P.d_slabruns;
+  a.slab_order = P.d_slaborder;
   a.twx = P.d_twx;
   a.twy = D.d_twy;
   a.twz = P.d_twz;
@@ -643,17 +693,24 @@ int occupancy(size_t lds) {
   return std::min(by_lds, 8);
 }
 
-void grids(const fftb_plan_s& P, const DirCfg& D, int& g1, int& g2) {
+// Static grids cover every task under the group-interleaved XCD mapping:
+// ceil(groups / 8) groups per XCD.
+void grids(const fftb_plan_s& P, const DirCfg& D, int& g1, int& g2, int& g3) {
+  const int G = D.reg2 ? (D.class_par ? D.n1 : D.nsplit) : 1;
   g1 = ((D.k1_tasks + 7) / 8) * 8;
-  g2 = ((D.k2_tasks + 7) / 8) * 8;
+  g2 = ((D.k2_tasks / G + 7) / 8) * 8 * G;
+  g3 = ((D.k3_tasks + 7) / 8) * 8;
   if (P.flags & FFTB_PLAN_BATCHED) {
     // persistent: enough blocks to fill the chip, at least one per XCD queue
     const int c1 = P.num_cus * occupancy(D.lds1);
     const int c2 = P.num_cus * occupancy(D.lds2);
+    const int c3 = P.num_cus * occupancy(0);
     g1 = std::max(8, std::min(c1, g1));
     g2 = std::max(8, std::min(c2, g2));
+    g3 = std::max(8, std::min(c3, g3));
     g1 = (g1 + 7) / 8 * 8;
     g2 = (g2 + 7) / 8 * 8;
+    g3 = (g3 + 7) / 8 * 8;
   }
 }
 
@@ -670,17 +727,24 @@ hipError_t get_event(fftb_plan_s* P, hipEvent_t* e) {
 // plane kernel then column kernel. Persistent kernels first reset their work
 // counters with a kernel (graph-safe, no memset node).
 hipError_t enqueue(fftb_plan_s* P, const KArgs& a, const DirCfg& D, bool inverse, int g1, int g2,
-                   hipStream_t st, bool profile) {
+                   int g3, hipStream_t st, bool profile) {
   const bool fp64 = P->dtype == FFTB_C128;
   hipError_t e = hipSuccess;
   if (a.persistent) {
     e = launch_reset(a.counters, st);
     if (e != hipSuccess) return e;
   }
-  const int order[2] = {inverse ? 1 : 2, inverse ? 2 : 1};
+  // which: 1 column kernel, 2 plane kernel, 3 forward class combine
+  int order[3] = {inverse ? 1 : 2, inverse ? 2 : 1, 0};
+  if (!inverse && D.fwd_cls) {
+    order[1] = 3;
+    order[2] = 1;
+  }
   for (int which : order) {
-    // kernel ids: 0 column inverse, 1 plane inverse, 2 plane forward, 3 column forward
-    const int kid = inverse ? (which == 1 ? 0 : 1) : (which == 2 ? 2 : 3);
+    if (which == 0) continue;
+    // kernel ids: 0 column inverse, 1 plane inverse, 2 plane forward, 3 column forward,
+    // 4 class combine forward
+    const int kid = which == 3 ? 4 : inverse ? (which == 1 ? 0 : 1) : (which == 2 ? 2 : 3);
     hipEvent_t ea = nullptr, eb = nullptr;
     if (profile) {
       if ((e = get_event(P, &ea)) != hipSuccess) return e;
@@ -688,10 +752,13 @@ hipError_t enqueue(fftb_plan_s* P, const KArgs& a, const DirCfg& D, bool inverse
       if ((e = hipEventRecord(ea, st)) != hipSuccess) return e;
     }
     const bool reg = which == 1 ? D.reg1 : D.reg2;
-    if (reg) {
+    if (which == 3) {
+      e = launch_combine(a, fp64, g3, 256, st);
+    } else if (reg) {
       e = launch_reg(which, a, inverse, fp64, which == 1 ? D.e1 : D.e2, which == 1 ? D.h1 : D.h2,
                      which == 1 ? g1 : g2, which == 1 ? std::min(D.threads, 256) : D.threads,
-                     which == 1 ? 0 : D.lds2, st, which == 1 ? D.mf1 : D.mf2);
+                     which == 1 ? 0 : D.lds2, st, which == 1 ? D.mf1 : D.mf2,
+                     which == 1 ? 0 : D.fold_m);
     } else {
       e = launch_kernel(which, a, inverse, fp64, which == 1 ? g1 : g2, D.threads,
                         which == 1 ? D.lds1 : D.lds2, st);
@@ -711,8 +778,8 @@ fftb_status run(fftb_plan_s* P, const void* in, void* out, void* stream, bool in
   if (!in || !out) return fail(FFTB_ERR_INVALID, "null data pointer");
   hipStream_t st = static_cast<hipStream_t>(stream);
   const DirCfg& D = P->dir[inverse ? 0 : 1];
-  int g1, g2;
-  grids(*P, D, g1, g2);
+  int g1, g2, g3;
+  grids(*P, D, g1, g2, g3);
   KArgs a = make_args(*P, D, in, out, inverse);
   if (P->flags & FFTB_PLAN_GRAPH) {
     auto& gc = P->gc[inverse ? 0 : 1];
@@ -725,7 +792,7 @@ fftb_status run(fftb_plan_s* P, const void* in, void* out, void* stream, bool in
       }
       hipError_t e = hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal);
       if (e != hipSuccess) return fail(FFTB_ERR_HIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
-      hipError_t el = enqueue(P, a, D, inverse, g1, g2, P->cap_stream, false);
+      hipError_t el = enqueue(P, a, D, inverse, g1, g2, g3, P->cap_stream, false);
       e = hipStreamEndCapture(P->cap_stream, &gc.graph);
       if (el != hipSuccess) return fail(FFTB_ERR_HIP, std::string("launch during capture: ") + hipGetErrorString(el));
       if (e != hipSuccess) return fail(FFTB_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
@@ -738,7 +805,7 @@ fftb_status run(fftb_plan_s* P, const void* in, void* out, void* stream, bool in
     if (e != hipSuccess) return fail(FFTB_ERR_HIP, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
     return FFTB_OK;
   }
-  hipError_t e = enqueue(P, a, D, inverse, g1, g2, st, P->profiling);
+  hipError_t e = enqueue(P, a, D, inverse, g1, g2, g3, st, P->profiling);
   if (e != hipSuccess) return fail(FFTB_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
   return FFTB_OK;
 }
@@ -841,9 +908,9 @@ std::vector<fftb_dir_tuning> candidates(const fftb_plan_s& P, bool inverse, cons
           t.path = 0;
           out.push_back(t);
         } else {
-          for (int acc : {1, 2}) {
+          for (int acc : {3, 1, 2}) {
             for (int extra : {0, 1}) {
-              if (acc == 2 && extra) continue;
+              if (acc != 1 && extra) continue;
               fftb_dir_tuning t = base;
               t.band_chunk = bc;
               t.y_classes = n1;
@@ -987,6 +1054,7 @@ fftb_status fftb_plan_create(fftb_plan* out, const int32_t dims[3], const fftb_s
         return fail(FFTB_ERR_INVALID, buf + err);
       }
       for (int k = 0; k < 3; ++k) P->sph[s].kpt[k] = spheres[s].kpt[k];
+      P->two_runs = P->two_runs && P->sph[s].two_runs;
       P->max_ncol = std::max(P->max_ncol, P->sph[s].ncol);
       P->max_nslab = std::max(P->max_nslab, P->sph[s].nslab);
       P->total_columns += P->sph[s].ncol;
@@ -1015,7 +1083,7 @@ fftb_status fftb_plan_create(fftb_plan* out, const int32_t dims[3], const fftb_s
       o.col_tile = D.lc;
       o.threads = D.threads;
       o.path = (D.reg1 && D.reg2) ? 2 : (D.reg1 || D.reg2) ? 0 : 1;
-      o.acc = d == 0 ? 0 : (D.reg2 && D.acc_lds) ? 1 : 2;
+      o.acc = d == 0 ? 0 : D.fwd_cls ? 3 : (D.reg2 && D.acc_lds) ? 1 : 2;
       o.splits = D.nsplit;
     }
     if (!(flags & FFTB_PLAN_HOST_ONLY)) {
@@ -1118,7 +1186,7 @@ fftb_status fftb_plan_get_profile(fftb_plan P, fftb_profile* out) {
     P->ev_pool.push_back(r.b);
   }
   P->prof_pending.clear();
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < 5; ++k) {
     out->launches[k] = P->prof_launches[k];
     out->total_ms[k] = P->prof_ms[k];
     P->prof_launches[k] = 0;

@@ -15,6 +15,30 @@ namespace fftb {
 
 constexpr int kMaxRadixDev = 16;
 
+// Task scheduling over the XCDs (the hardware places blocks on the 8 XCDs
+// round-robin by block index). Tasks come in groups of G consecutive indices
+// that read the same input through L2 (the y classes of one plane and band
+// chunk); group g runs on XCD g mod 8 and every XCD walks its groups in order,
+// so at any time the chip works on neighbouring groups: all band chunks of the
+// same planes, whose pieces of each band vector then reach HBM together.
+__device__ __forceinline__ int xcd_task(int q, int k, int G) {
+  return (((k / G) << 3) + q) * G + k % G;
+}
+// one block per task: block b is the k = b/8 th block on XCD q = b mod 8
+__device__ __forceinline__ int static_task_g(int total, int G) {
+  const int t = xcd_task(blockIdx.x & 7, blockIdx.x >> 3, G);
+  return t < total ? t : -1;
+}
+// persistent blocks: one counter per XCD; the task index grows with the
+// counter, so the first index past the end ends that XCD's queue
+__device__ __forceinline__ int dynamic_task_g(unsigned int* counters, int total, int G) {
+  const int q = blockIdx.x & 7;
+  const unsigned int idx = atomicAdd(&counters[q], 1u);
+  if (idx >= static_cast<unsigned int>(total)) return -1;
+  const int t = xcd_task(q, static_cast<int>(idx), G);
+  return t < total ? t : -1;
+}
+
 template <typename T>
 struct alignas(2 * sizeof(T)) cpx {
   T re, im;

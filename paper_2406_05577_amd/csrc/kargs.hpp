@@ -21,6 +21,7 @@ struct SphereDesc {
   int64_t sph_off;     // first S[g][b] of this sphere in the sphere buffer
   int64_t grid_off;    // first G[z][y][x][b] in the grid buffer
   int64_t col_off;     // first element of this sphere's column scratch
+  int64_t zp_off;      // first element of this sphere's forward class partials
   int32_t gidx_off;    // ncol*nz table: coefficient index of (column, z) or -1
   int32_t colidx_off;  // nslab*ny table: column index of (slab, y) or -1
   int32_t colmeta_off; // per-column slab index and y
@@ -31,8 +32,10 @@ struct SphereDesc {
   int32_t nchunk;      // ceil(nb / band_chunk)
   int32_t k1_start, k1_end;  // task range of the column kernel
   int32_t k2_start, k2_end;  // task range of the plane kernel
+  int32_t k3_start, k3_end;  // task range of the forward class combine
   int32_t slab_off;    // nslab+1 table: first column of each occupied slab
   int32_t split_off;   // nsplit+1 table: first slab of each forward column split
+  int32_t sl_off;      // first slab of this sphere in the per-slab tables
 };
 
 struct KArgs {
@@ -42,13 +45,15 @@ struct KArgs {
   int lx;            // rows per x batch in the plane kernel
   int lc;            // columns per column-kernel task
   int nsph;
-  int k1_tasks, k2_tasks;
+  int k1_tasks, k2_tasks, k3_tasks;
   int persistent;
   int lds_P, lds_X0, lds_X1;  // element offsets of LDS regions (S starts at 0)
   int lds_acc;       // element offset of the forward column accumulators
   int acc_lds;       // forward plane kernel accumulates columns in LDS
   int sx;            // element stride between slab lines of the class slab
   int nsplit;        // forward plane tasks per (plane, chunk): slab ranges with their columns
+  int fwd_cls;       // forward: class partials Z[z][xi][j][r], combined into columns by K3
+  int g2;            // plane-kernel tasks per L2-sharing group (scheduling)
   AxisDev ax, ay, az;
   const SphereDesc* sph;
   const int32_t* gidx;
@@ -58,6 +63,8 @@ struct KArgs {
   const int32_t* xinv;
   const int32_t* slabstart;
   const int32_t* splits;
+  const int32_t* slab_runs;  // 4 per slab: y runs [a0, a1), [b0, b1) in column order
+  const int32_t* slab_order; // per sphere: slab indices by descending column count
   const void* twx;      // forward-sign twiddles (double pairs, or FP32 hi)
   const void* twy;
   const void* twz;
@@ -74,7 +81,7 @@ struct KArgs {
   void* out;
   void* col;            // column scratch
   double scale;         // 1/N for the forward direction
-  unsigned int* counters;  // 16 work counters (persistent mode)
+  unsigned int* counters;  // 24 work counters (persistent mode): 8 per kernel
 };
 
 }  // namespace fftb

@@ -98,24 +98,6 @@ __device__ __forceinline__ void axis_run(const AxisDev& ap, int nlines, const cp
                   bcl, LdsSrc<T>{from, n, bcl}, gdst);
 }
 
-// ---------------------------------------------------------------------------
-// Task scheduling. Non-persistent: block b takes task (b mod 8)*per + b/8, so
-// the blocks that the hardware places on one XCD walk a contiguous task range
-// (same plane, neighbouring band chunks). Persistent: blocks b with the same
-// b mod 8 drain one queue of that range through an atomic counter.
-__device__ __forceinline__ int static_task(int total) {
-  const int per = (total + 7) >> 3;
-  const int t = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-  return t < total ? t : -1;
-}
-__device__ __forceinline__ int dynamic_task(unsigned int* counters, int total) {
-  const int per = (total + 7) >> 3;
-  const int q = blockIdx.x & 7;
-  const unsigned int idx = atomicAdd(&counters[q], 1u);
-  const long t = static_cast<long>(q) * per + idx;
-  return (static_cast<int>(idx) < per && t < total) ? static_cast<int>(t) : -1;
-}
-
 __device__ __forceinline__ int find_sphere_k1(const KArgs& a, int t) {
   int s = 0;
   while (s + 1 < a.nsph && t >= a.sph[s].k1_end) ++s;
@@ -136,8 +118,7 @@ __device__ void k1_task(const KArgs& a, int t, cpx<T>* lds) {
   const int s = find_sphere_k1(a, t);
   const SphereDesc d = a.sph[s];
   const int lt = t - d.k1_start;
-  const int ncb = (d.ncol + a.lc - 1) / a.lc;
-  const int cb = lt % ncb, chunk = lt / ncb;
+  const int chunk = lt % d.nchunk, cb = lt / d.nchunk;
   const int c0 = cb * a.lc;
   const int nl = min(a.lc, d.ncol - c0);
   const int bcl = a.bcl, bc = 1 << bcl;
@@ -149,7 +130,7 @@ __device__ void k1_task(const KArgs& a, int t, cpx<T>* lds) {
   const cpx<T>* twlo = reinterpret_cast<const cpx<T>*>(a.twz_lo);
   cpx<T>* b_0 = lds;
   cpx<T>* b_1 = lds + ((a.lc * nz) << bcl);
-  const int64_t colbase = static_cast<int64_t>(chunk) * nz * ncol;
+  const int64_t nbp = d.nchunk << bcl;  // padded band vector per (z, column)
   if constexpr (S > 0) {
     const cpx<T>* __restrict__ in = reinterpret_cast<const cpx<T>*>(a.in) + d.sph_off;
     auto gsrc = [=](int line, int z, int bl) -> cpx<T> {
@@ -159,14 +140,14 @@ __device__ void k1_task(const KArgs& a, int t, cpx<T>* lds) {
       return cpx<T>{0, 0};
     };
     auto gdst = [=](int line, int z, int bl, cpx<T> v) {
-      colbuf[((colbase + static_cast<int64_t>(z) * ncol + c0 + line) << bcl) + bl] = v;
+      colbuf[(static_cast<int64_t>(z) * ncol + c0 + line) * nbp + b0 + bl] = v;
     };
     axis_run<S, T>(a.az, nl, tw, twlo, bcl, b_0, b_1, gsrc, gdst);
   } else {
     cpx<T>* __restrict__ out = reinterpret_cast<cpx<T>*>(a.out) + d.sph_off;
     const T sc = static_cast<T>(a.scale);
     auto gsrc = [=](int line, int z, int bl) -> cpx<T> {
-      return colbuf[((colbase + static_cast<int64_t>(z) * ncol + c0 + line) << bcl) + bl];
+      return colbuf[(static_cast<int64_t>(z) * ncol + c0 + line) * nbp + b0 + bl];
     };
     auto gdst = [=](int line, int z, int bl, cpx<T> v) {
       const int g = gidx[(c0 + line) * nz + z];
@@ -200,8 +181,8 @@ __device__ void k2_task(const KArgs& a, int t, cpx<T>* lds) {
   const int32_t* __restrict__ xinv = a.xinv + d.xinv_off;
   const int32_t* __restrict__ cxi = a.col_xi + d.colmeta_off;
   const int32_t* __restrict__ cy = a.col_y + d.colmeta_off;
-  cpx<T>* colp = reinterpret_cast<cpx<T>*>(a.col) + d.col_off +
-                 ((static_cast<int64_t>(chunk) * a.nz + z) * ncol << bcl);
+  const int64_t nbp = d.nchunk << bcl;
+  cpx<T>* colp = reinterpret_cast<cpx<T>*>(a.col) + d.col_off + static_cast<int64_t>(z) * ncol * nbp + b0;
   const cpx<T>* twx = reinterpret_cast<const cpx<T>*>(a.twx);
   const cpx<T>* twxl = reinterpret_cast<const cpx<T>*>(a.twx_lo);
   const cpx<T>* twy = reinterpret_cast<const cpx<T>*>(a.twy);
@@ -228,7 +209,7 @@ __device__ void k2_task(const KArgs& a, int t, cpx<T>* lds) {
           const int y = j2 + m * tt;
           const int c = colidx[xi * ny + y];
           if (c >= 0) {
-            const cpx<T> v = colp[(c << bcl) + bl];
+            const cpx<T> v = colp[static_cast<int64_t>(c) * nbp + bl];
             acc = cadd(acc, twmul<S>(v, twf, twfl, (y * r) % ny));
           }
         }
@@ -307,7 +288,7 @@ __device__ void k2_task(const KArgs& a, int t, cpx<T>* lds) {
         const int xi = cxi[c], y = cy[c];
         const int ym = y % m;
         cpx<T> v = twmul<S>(Yb[((xi * m + ym) << bcl) + bl], twf, twfl, (y * r) % ny);
-        cpx<T>* p = colp + ((static_cast<int64_t>(c) << bcl) + bl);
+        cpx<T>* p = colp + (static_cast<int64_t>(c) * nbp + bl);
         if (r > 0) v = cadd(v, *p);
         *p = v;
       }
@@ -321,13 +302,13 @@ __global__ void __launch_bounds__(256) k1_kernel(const KArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
   if (!a.persistent) {
-    const int t = static_task(a.k1_tasks);
+    const int t = static_task_g(a.k1_tasks, 1);
     if (t >= 0) k1_task<S, T>(a, t, lds);
     return;
   }
   __shared__ int sh_task;
   for (;;) {
-    if (threadIdx.x == 0) sh_task = dynamic_task(a.counters, a.k1_tasks);
+    if (threadIdx.x == 0) sh_task = dynamic_task_g(a.counters, a.k1_tasks, 1);
     __syncthreads();
     const int t = sh_task;
     __syncthreads();
@@ -342,13 +323,13 @@ __global__ void __launch_bounds__(256) k2_kernel(const KArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
   if (!a.persistent) {
-    const int t = static_task(a.k2_tasks);
+    const int t = static_task_g(a.k2_tasks, 1);
     if (t >= 0) k2_task<S, T>(a, t, lds);
     return;
   }
   __shared__ int sh_task;
   for (;;) {
-    if (threadIdx.x == 0) sh_task = dynamic_task(a.counters + 8, a.k2_tasks);
+    if (threadIdx.x == 0) sh_task = dynamic_task_g(a.counters + 8, a.k2_tasks, 1);
     __syncthreads();
     const int t = sh_task;
     __syncthreads();
@@ -359,7 +340,7 @@ __global__ void __launch_bounds__(256) k2_kernel(const KArgs a) {
 }
 
 __global__ void reset_counters(unsigned int* c) {
-  if (threadIdx.x < 16) c[threadIdx.x] = 0u;
+  if (threadIdx.x < 24) c[threadIdx.x] = 0u;
 }
 
 // ---------------------------------------------------------------------------

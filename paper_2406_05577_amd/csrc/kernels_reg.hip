@@ -12,11 +12,16 @@
 // y with length m = ny/n1, then every row y = r + n1*k2 is transformed along x
 // over the full grid and written. The n1 tasks of one (plane, chunk) are
 // consecutive, so the blocks on one XCD read the same column data from L2.
-// Plane kernel, forward: task = (plane z, band chunk); for each class r the
-// rows y = r + n1*k2 are transformed along x keeping the occupied x only, then
-// along y with length m, and the class's contribution w_ny^{-y*r} * Y[xi][y mod m]
-// is accumulated into each column (a decimation-in-time combination over the
-// classes, each column owned by one thread).
+// Plane kernel, forward, class-parallel (default): task = (plane z, band chunk,
+// y class r). The rows y = r + n1*k2 are transformed along x keeping the
+// occupied x only, then along y with length m; the result, multiplied by
+// w_ny^{-j*r}, is stored as the class partial Z_r[xi][j]. The combine kernel
+// then forms each column value y = j + m*t as the length-n1 DFT over the
+// classes, sum_r w_n1^{-t*r} Z_r[xi][j] (a decimation-in-time split of the
+// y transform), and the column kernel runs the z transforms.
+// Plane kernel, forward, accumulating: task = (plane z, band chunk, column
+// split); for each class r the split's columns accumulate the class's
+// contribution w_ny^{-y*r} * Y[xi][y mod m] in LDS or in global memory.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -37,17 +42,12 @@ __device__ __forceinline__ int find_sphere_k2r(const KArgs& a, int t) {
   return s;
 }
 
-__device__ __forceinline__ int static_task_r(int total) {
-  const int per = (total + 7) >> 3;
-  const int t = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-  return t < total ? t : -1;
-}
-__device__ __forceinline__ int dynamic_task_r(unsigned int* counters, int total) {
-  const int per = (total + 7) >> 3;
-  const int q = blockIdx.x & 7;
-  const unsigned int idx = atomicAdd(&counters[q], 1u);
-  const long t = static_cast<long>(q) * per + idx;
-  return (static_cast<int>(idx) < per && t < total) ? static_cast<int>(t) : -1;
+// floor(n / d) for 0 <= n < 2^22 through a float reciprocal and one correction
+__device__ __forceinline__ int div_small(int n, int d, float inv_d) {
+  int q = static_cast<int>(static_cast<float>(n) * inv_d);
+  const int rem = n - q * d;
+  q += (rem >= d) - (rem < 0);
+  return q;
 }
 
 // ---------------------------------------------------------------------------
@@ -57,16 +57,16 @@ __device__ void k1r_task(const KArgs& a, int t) {
   const int s = find_sphere_k1r(a, t);
   const SphereDesc d = a.sph[s];
   const int lt = t - d.k1_start;
-  const int ncb = (d.ncol + a.lc - 1) / a.lc;
-  const int cb = lt % ncb, chunk = lt / ncb;
+  const int chunk = lt % d.nchunk, cb = lt / d.nchunk;
   const int c0 = cb * a.lc;
   const int nl = min(a.lc, d.ncol - c0);
   const int bcl = a.bcl, bmask = (1 << bcl) - 1;
   const int b0 = chunk << bcl;
   const int nz = a.nz, nb = d.nb, ncol = d.ncol;
   const int32_t* __restrict__ gidx = a.gidx + d.gidx_off;
-  cpx<T>* __restrict__ colbuf = reinterpret_cast<cpx<T>*>(a.col) + d.col_off +
-                                ((static_cast<int64_t>(chunk) * nz * ncol) << bcl);
+  // column scratch: one padded band vector (nbp values) per (z, column)
+  const int nbp = d.nchunk << bcl;
+  cpx<T>* __restrict__ colbuf = reinterpret_cast<cpx<T>*>(a.col) + d.col_off + b0;
   const cpx<T>* rootz = reinterpret_cast<const cpx<T>*>(a.rootz);
   const cpx<T>* rootz_lo = reinterpret_cast<const cpx<T>*>(a.rootz_lo);
   const int items = (nl << bcl) * H;
@@ -91,7 +91,7 @@ __device__ void k1r_task(const KArgs& a, int t) {
     } else {
 #pragma unroll
       for (int j = 0; j < E; ++j)
-        v[j] = valid ? colbuf[((static_cast<int64_t>(h + H * j) * ncol + c) << bcl) + bl]
+        v[j] = valid ? colbuf[(static_cast<int64_t>(h + H * j) * ncol + c) * nbp + bl]
                      : cpx<T>{0, 0};
     }
     line_fft<E, H, S, T, MF>(v, h, rootz, rootz_lo);
@@ -100,7 +100,7 @@ __device__ void k1r_task(const KArgs& a, int t) {
     if constexpr (S > 0) {
 #pragma unroll
       for (int k = 0; k < E; ++k)
-        colbuf[((static_cast<int64_t>(k + E * q) * ncol + c) << bcl) + bl] = v[k];
+        colbuf[(static_cast<int64_t>(k + E * q) * ncol + c) * nbp + bl] = v[k];
     } else {
       cpx<T>* __restrict__ out = reinterpret_cast<cpx<T>*>(a.out) + d.sph_off;
       const T sc = static_cast<T>(a.scale);
@@ -114,7 +114,19 @@ __device__ void k1r_task(const KArgs& a, int t) {
 }
 
 // ---------------------------------------------------------------------------
-template <typename T, int E, int H, bool MF>
+// Column index of y in a slab whose sorted y values are the runs [a0, a1) and
+// [b0, b1) starting at column cs, or -1.
+__device__ __forceinline__ int run_col(int y, int cs, int a0, int a1, int b0, int b1) {
+  const unsigned da = static_cast<unsigned>(y - a0);
+  if (da < static_cast<unsigned>(a1 - a0)) return cs + static_cast<int>(da);
+  const unsigned db = static_cast<unsigned>(y - b0);
+  return db < static_cast<unsigned>(b1 - b0) ? cs + (a1 - a0) + static_cast<int>(db) : -1;
+}
+
+// M > 0: the class length m = M is a compile-time constant and every slab's
+// columns form at most two runs of consecutive y; one thread folds and
+// transforms a whole (slab, band) line in registers. M == 0: generic fold.
+template <typename T, int E, int H, bool MF, int M>
 __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S) {
   constexpr int L = log2_const<H>();
   const int s = find_sphere_k2r(a, t);
@@ -129,73 +141,128 @@ __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S) {
   const int nx = a.nx, ny = a.ny, sx = a.sx;
   const int nb = d.nb, ncol = d.ncol, nslab = d.nslab;
   const int32_t* __restrict__ xinv = a.xinv + d.xinv_off;
-  const int32_t* __restrict__ cy = a.col_y + d.colmeta_off;
-  const int32_t* __restrict__ sst = a.slabstart + d.slab_off;
+  const int nbp = d.nchunk << bcl;
   const cpx<T>* __restrict__ colp = reinterpret_cast<const cpx<T>*>(a.col) + d.col_off +
-                                    (((static_cast<int64_t>(chunk) * a.nz + z) * ncol) << bcl);
+                                    static_cast<int64_t>(z) * ncol * nbp + b0;
   const cpx<T>* twf = reinterpret_cast<const cpx<T>*>(a.twf);
   const cpx<T>* twfl = reinterpret_cast<const cpx<T>*>(a.twf_lo);
   const cpx<T>* rootx = reinterpret_cast<const cpx<T>*>(a.rootx);
   const cpx<T>* rootx_lo = reinterpret_cast<const cpx<T>*>(a.rootx_lo);
 
-  // fold the slab's columns into class r, then y-IFFT of length m (one thread per line)
-  const int nlines = nslab << bcl;
-  for (int it = threadIdx.x; it < nlines; it += blockDim.x) {
-    const int bl = it & bmask, xi = it >> bcl;
-    cpx<T>* line = S + xi * sx + bl;
-    for (int j = 0; j < m; ++j) line[j << bcl] = cpx<T>{0, 0};
-    const int ce = sst[xi + 1];
-    int c = sst[xi];
-    // batches of FB columns: all loads in flight before the LDS updates
-    constexpr int FB = sizeof(T) == 8 ? 8 : 16;
-    for (; c + FB <= ce; c += FB) {
-      cpx<T> v[FB];
-      int yy[FB];
+  if constexpr (M > 0) {
+    // per (slab, band) line, heaviest slabs first: for each block tb of M
+    // consecutive y (y = k + M*tb) that meets the slab, u[k] += col(y) * w_n1^{+tb*r};
+    // then u[k] *= w_ny^{+k*r} and the length-M IFFT, written once to S
+    const int32_t* __restrict__ runs = a.slab_runs + 4 * d.sl_off;
+    const int32_t* __restrict__ order = a.slab_order + d.sl_off;
+    const int32_t* __restrict__ sst = a.slabstart + d.slab_off;
+    const int mr = M * r;  // w_n1^{tb*r} = w_ny^{M*tb*r}
+    const int nlines = nslab << bcl;
+    for (int it = threadIdx.x; it < nlines; it += blockDim.x) {
+      const int bl = it & bmask;
+      const int xi = order[it >> bcl];
+      const int cs = sst[xi];
+      const int a0 = runs[4 * xi], a1 = runs[4 * xi + 1];
+      const int b0 = runs[4 * xi + 2], b1 = runs[4 * xi + 3];
+      cpx<T> u[M];
 #pragma unroll
-      for (int u = 0; u < FB; ++u) {
-        yy[u] = cy[c + u];
-        v[u] = colp[((c + u) << bcl) + bl];
+      for (int k = 0; k < M; ++k) u[k] = cpx<T>{0, 0};
+      int idx = 0;
+      for (int tb = 0; tb < n1; ++tb, idx = (idx + mr >= ny) ? idx + mr - ny : idx + mr) {
+        const int y0 = tb * M;
+        const bool hit = (y0 < a1 && y0 + M > a0) || (y0 < b1 && y0 + M > b0);
+        if (!hit) continue;
+        cpx<T> v[M];
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+          const int c = run_col(y0 + k, cs, a0, a1, b0, b1);
+          v[k] = c >= 0 ? colp[static_cast<int64_t>(c) * nbp + bl] : cpx<T>{0, 0};
+        }
+        cpx<T> w = twf[idx];
+        w.im = -w.im;
+        if constexpr (std::is_same<T, float>::value) {
+          cpx<T> wl = twfl[idx];
+          wl.im = -wl.im;
+#pragma unroll
+          for (int k = 0; k < M; ++k) u[k] = cadd(u[k], cadd(cmul(v[k], w), cmul(v[k], wl)));
+        } else {
+#pragma unroll
+          for (int k = 0; k < M; ++k) u[k] = cadd(u[k], cmul(v[k], w));
+        }
       }
 #pragma unroll
-      for (int u = 0; u < FB; ++u) {
-        cpx<T>* p = line + ((yy[u] % m) << bcl);
-        *p = cadd(*p, twmul<+1>(v[u], twf, twfl, (yy[u] * r) % ny));
+      for (int k = 1; k < M; ++k) u[k] = twmul<+1>(u[k], twf, twfl, k * r);
+      dft<M, +1>(u);
+      cpx<T>* line = S + xi * sx + bl;
+#pragma unroll
+      for (int k = 0; k < M; ++k) line[k << bcl] = u[k];
+    }
+    __syncthreads();
+  } else {
+    const int32_t* __restrict__ cidx = a.colidx + d.colidx_off;
+
+    // fold, one output per thread:
+    //   F_r[xi][j] = w_ny^{+j*r} * sum_t col(xi, y = j + m*t) * w_n1^{+t*r}
+    // (the first stage of a decimation-in-frequency split of the y transform,
+    // evaluated for the single output class r; absent columns are zero)
+    const int mr = m * r;  // w_n1^{t*r} = w_ny^{m*t*r}
+    const float inv_m = 1.0f / static_cast<float>(m);
+    const int nfold = (nslab * m) << bcl;
+    for (int it = threadIdx.x; it < nfold; it += blockDim.x) {
+      const int bl = it & bmask;
+      const int jx = it >> bcl;
+      const int xi = div_small(jx, m, inv_m);
+      const int j = jx - xi * m;
+      const int32_t* __restrict__ crow = cidx + xi * ny + j;
+      cpx<T> acc{0, 0};
+      int idx = 0;
+  #pragma unroll 4
+      for (int tt = 0; tt < n1; ++tt) {
+        const int ci = crow[tt * m];
+        if (ci >= 0) acc = cadd(acc, twmul<+1>(colp[static_cast<int64_t>(ci) * nbp + bl], twf, twfl, idx));
+        idx += mr;
+        if (idx >= ny) idx -= ny;
       }
+      S[xi * sx + (j << bcl) + bl] = twmul<+1>(acc, twf, twfl, j * r);
     }
-    for (; c < ce; ++c) {
-      const int y = cy[c];
-      const cpx<T> v = colp[(c << bcl) + bl];
-      cpx<T>* p = line + ((y % m) << bcl);
-      *p = cadd(*p, twmul<+1>(v, twf, twfl, (y * r) % ny));
+    __syncthreads();
+    // y-IFFT of length m per (slab, band) line, in place
+    const int nlines = nslab << bcl;
+    for (int it = threadIdx.x; it < nlines; it += blockDim.x) {
+      const int bl = it & bmask, xi = it >> bcl;
+      cpx<T>* line = S + xi * sx + bl;
+      cpx<T> u[kMaxRadixDev];
+  #pragma unroll
+      for (int j = 0; j < kMaxRadixDev; ++j)
+        if (j < m) u[j] = line[j << bcl];
+      butterfly<+1>(m, u);
+  #pragma unroll
+      for (int j = 0; j < kMaxRadixDev; ++j)
+        if (j < m) line[j << bcl] = u[j];
     }
-    cpx<T> u[kMaxRadixDev];
-#pragma unroll
-    for (int j = 0; j < kMaxRadixDev; ++j)
-      if (j < m) u[j] = line[j << bcl];
-    butterfly<+1>(m, u);
-#pragma unroll
-    for (int j = 0; j < kMaxRadixDev; ++j)
-      if (j < m) line[j << bcl] = u[j];
+    __syncthreads();
   }
-  __syncthreads();
-  // x-IFFT of the class's rows, written to the grid
+  // x-IFFT of the class's rows, written to the grid. Lane h of a line keeps
+  // the same h for every row, so its slab lookups are loaded once.
   cpx<T>* __restrict__ gout = reinterpret_cast<cpx<T>*>(a.out) + d.grid_off;
-  const int items = (m << bcl) * H;
-  const int iters = MF ? ((items + 63) & ~63) : items;
-  for (int it = threadIdx.x; it < iters; it += blockDim.x) {
-    const bool valid = !MF || it < items;
-    const int iv = valid ? it : 0;
-    const int h = iv % H;
-    const int rest = iv / H;
-    const int bl = rest & bmask, k2 = rest >> bcl;
+  const int h = threadIdx.x % H;
+  const int q = bitrev_bits(h, L);
+  int xs[E];
+#pragma unroll
+  for (int j = 0; j < E; ++j) xs[j] = xinv[h + H * j];
+  const int nrest = m << bcl;
+  const int per_wave = 64 / H;
+  const int nrest_p = MF ? (nrest + per_wave - 1) / per_wave * per_wave : nrest;
+  const int rstep = blockDim.x / H;
+  for (int rest = threadIdx.x / H; rest < nrest_p; rest += rstep) {
+    const bool valid = rest < nrest;
+    const int rv = valid ? rest : 0;
+    const int bl = rv & bmask, k2 = rv >> bcl;
     cpx<T> v[E];
 #pragma unroll
-    for (int j = 0; j < E; ++j) {
-      const int xi = xinv[h + H * j];
-      v[j] = (valid && xi >= 0) ? S[xi * sx + (k2 << bcl) + bl] : cpx<T>{0, 0};
-    }
+    for (int j = 0; j < E; ++j)
+      v[j] = (valid && xs[j] >= 0) ? S[xs[j] * sx + (k2 << bcl) + bl] : cpx<T>{0, 0};
     line_fft<E, H, +1, T, MF>(v, h, rootx, rootx_lo);
-    const int q = bitrev_bits(h, L);
     const int y = r + n1 * k2;
     const int b = b0 + bl;
     if (valid && b < nb) {
@@ -207,9 +274,97 @@ __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S) {
 }
 
 // ---------------------------------------------------------------------------
+// Forward x transform of the class rows y = r + n1*k2 (k2 < m) of plane z for
+// the bands b0 + bl, keeping the occupied x of slabs [x_lo, x_hi) as
+// S[xi - x_lo][k2][bl]. Lane h of a line keeps the same h for every row, so
+// its slab lookups are loaded once.
+template <typename T, int E, int H, bool MF>
+__device__ __forceinline__ void fwd_x_rows(const KArgs& a, const cpx<T>* __restrict__ gin,
+                                           const int32_t* __restrict__ xinv, cpx<T>* S, int r,
+                                           int z, int b0, int nb, int x_lo, int x_hi) {
+  constexpr int L = log2_const<H>();
+  const int bcl = a.bcl, bmask = (1 << bcl) - 1;
+  const int nx = a.nx, ny = a.ny, n1 = a.n1, sx = a.sx;
+  const cpx<T>* rootx = reinterpret_cast<const cpx<T>*>(a.rootx);
+  const cpx<T>* rootx_lo = reinterpret_cast<const cpx<T>*>(a.rootx_lo);
+  const int h = threadIdx.x % H;
+  const int q = bitrev_bits(h, L);
+  int xs[E];
+#pragma unroll
+  for (int k = 0; k < E; ++k) {
+    const int xi = xinv[k + E * q] - x_lo;
+    xs[k] = (xi >= 0 && xi < x_hi - x_lo) ? xi : -1;
+  }
+  const int nrest = a.m << bcl;
+  const int per_wave = 64 / H;
+  const int nrest_p = MF ? (nrest + per_wave - 1) / per_wave * per_wave : nrest;
+  const int rstep = blockDim.x / H;
+  for (int rest = threadIdx.x / H; rest < nrest_p; rest += rstep) {
+    const bool valid = rest < nrest;
+    const int rv = valid ? rest : 0;
+    const int bl = rv & bmask, k2 = rv >> bcl;
+    const int y = r + n1 * k2;
+    const int b = b0 + bl;
+    const bool ld = valid && b < nb;
+    cpx<T> v[E];
+    const cpx<T>* row = gin + static_cast<int64_t>(z * ny + y) * nx * nb + b;
+#pragma unroll
+    for (int j = 0; j < E; ++j)
+      v[j] = ld ? row[static_cast<int64_t>(h + H * j) * nb] : cpx<T>{0, 0};
+    line_fft<E, H, -1, T, MF>(v, h, rootx, rootx_lo);
+    if (!valid) continue;
+#pragma unroll
+    for (int k = 0; k < E; ++k)
+      if (xs[k] >= 0) S[xs[k] * sx + (k2 << bcl) + bl] = v[k];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Class-parallel forward task (plane z, chunk, class r): x transform of the
+// class rows, y transform of length m per (slab, band) line, then the class
+// partial Z_r[xi][j] = w_ny^{-j*r} * Y[xi][j] stored as Z[z][xi][j][r][band].
+template <typename T, int E, int H, bool MF>
+__device__ void k2r_fwd_cls_task(const KArgs& a, int t, cpx<T>* S) {
+  const int s = find_sphere_k2r(a, t);
+  const SphereDesc d = a.sph[s];
+  const int lt = t - d.k2_start;
+  const int n1 = a.n1, m = a.m;
+  const int r = lt % n1;
+  const int rest0 = lt / n1;
+  const int chunk = rest0 % d.nchunk, z = rest0 / d.nchunk;
+  const int bcl = a.bcl, bmask = (1 << bcl) - 1;
+  const int b0 = chunk << bcl;
+  const int ny = a.ny, sx = a.sx;
+  const int nb = d.nb, nslab = d.nslab;
+  const int32_t* __restrict__ xinv = a.xinv + d.xinv_off;
+  const cpx<T>* __restrict__ gin = reinterpret_cast<const cpx<T>*>(a.in) + d.grid_off;
+  const cpx<T>* twf = reinterpret_cast<const cpx<T>*>(a.twf);
+  const cpx<T>* twfl = reinterpret_cast<const cpx<T>*>(a.twf_lo);
+  const int nbp = d.nchunk << bcl;
+  cpx<T>* __restrict__ zp = reinterpret_cast<cpx<T>*>(a.col) + d.zp_off +
+                            (static_cast<int64_t>(z) * nslab * ny + r) * nbp + b0;
+
+  fwd_x_rows<T, E, H, MF>(a, gin, xinv, S, r, z, b0, nb, 0, nslab);
+  __syncthreads();
+  const int nlines = nslab << bcl;
+  for (int it = threadIdx.x; it < nlines; it += blockDim.x) {
+    const int bl = it & bmask, xi = it >> bcl;
+    const cpx<T>* line = S + xi * sx + bl;
+    cpx<T> u[kMaxRadixDev];
+#pragma unroll
+    for (int j = 0; j < kMaxRadixDev; ++j)
+      if (j < m) u[j] = line[j << bcl];
+    butterfly<-1>(m, u);
+    cpx<T>* __restrict__ zl = zp + static_cast<int64_t>(xi) * ny * nbp + bl;
+#pragma unroll
+    for (int j = 0; j < kMaxRadixDev; ++j)
+      if (j < m) zl[j * n1 * nbp] = twmul<-1>(u[j], twf, twfl, j * r);
+  }
+}
+
+// ---------------------------------------------------------------------------
 template <typename T, int E, int H, bool MF>
 __device__ void k2r_fwd_task(const KArgs& a, int t, cpx<T>* S) {
-  constexpr int L = log2_const<H>();
   const int s = find_sphere_k2r(a, t);
   const SphereDesc d = a.sph[s];
   const int lt = t - d.k2_start;
@@ -220,50 +375,24 @@ __device__ void k2r_fwd_task(const KArgs& a, int t, cpx<T>* S) {
   const int x_lo = a.splits[d.split_off + q_split], x_hi = a.splits[d.split_off + q_split + 1];
   const int bcl = a.bcl, bmask = (1 << bcl) - 1;
   const int b0 = chunk << bcl;
-  const int nx = a.nx, ny = a.ny, n1 = a.n1, m = a.m, sx = a.sx;
-  const int nb = d.nb, ncol = d.ncol, nslab = d.nslab;
+  const int ny = a.ny, n1 = a.n1, m = a.m, sx = a.sx;
+  const int nb = d.nb, ncol = d.ncol;
   const int32_t* __restrict__ xinv = a.xinv + d.xinv_off;
   const int32_t* __restrict__ cy = a.col_y + d.colmeta_off;
   const int32_t* __restrict__ cxi = a.col_xi + d.colmeta_off;
   const int32_t* __restrict__ sst = a.slabstart + d.slab_off;
+  const int nbp = d.nchunk << bcl;
   cpx<T>* __restrict__ colp = reinterpret_cast<cpx<T>*>(a.col) + d.col_off +
-                              (((static_cast<int64_t>(chunk) * a.nz + z) * ncol) << bcl);
+                              static_cast<int64_t>(z) * ncol * nbp + b0;
   const cpx<T>* __restrict__ gin = reinterpret_cast<const cpx<T>*>(a.in) + d.grid_off;
   const cpx<T>* twf = reinterpret_cast<const cpx<T>*>(a.twf);
   const cpx<T>* twfl = reinterpret_cast<const cpx<T>*>(a.twf_lo);
-  const cpx<T>* rootx = reinterpret_cast<const cpx<T>*>(a.rootx);
-  const cpx<T>* rootx_lo = reinterpret_cast<const cpx<T>*>(a.rootx_lo);
   cpx<T>* acc = S + a.lds_acc;
   const bool acc_lds = a.acc_lds != 0;
   const int c_lo = sst[x_lo];
-  (void)nslab;
 
   for (int r = 0; r < n1; ++r) {
-    // x-FFT of the class's rows, keeping the occupied x
-    const int items = (m << bcl) * H;
-    const int iters = MF ? ((items + 63) & ~63) : items;
-    for (int it = threadIdx.x; it < iters; it += blockDim.x) {
-      const bool valid = !MF || it < items;
-      const int iv = valid ? it : 0;
-      const int h = iv % H;
-      const int rest = iv / H;
-      const int bl = rest & bmask, k2 = rest >> bcl;
-      const int y = r + n1 * k2;
-      const int b = b0 + bl;
-      cpx<T> v[E];
-      const cpx<T>* row = gin + static_cast<int64_t>(z * ny + y) * nx * nb + b;
-#pragma unroll
-      for (int j = 0; j < E; ++j)
-        v[j] = (valid && b < nb) ? row[static_cast<int64_t>(h + H * j) * nb] : cpx<T>{0, 0};
-      line_fft<E, H, -1, T, MF>(v, h, rootx, rootx_lo);
-      const int q = bitrev_bits(h, L);
-      if (!valid) continue;
-#pragma unroll
-      for (int k = 0; k < E; ++k) {
-        const int xi = xinv[k + E * q] - x_lo;
-        if (xi >= 0 && xi < x_hi - x_lo) S[xi * sx + (k2 << bcl) + bl] = v[k];
-      }
-    }
+    fwd_x_rows<T, E, H, MF>(a, gin, xinv, S, r, z, b0, nb, x_lo, x_hi);
     __syncthreads();
     // y-FFT of length m per occupied x of the split, in place
     const int nlines = (x_hi - x_lo) << bcl;
@@ -289,7 +418,7 @@ __device__ void k2r_fwd_task(const KArgs& a, int t, cpx<T>* S) {
       const int y = cy[c];
       const cpx<T> val =
           twmul<-1>(S[(cxi[c] - x_lo) * sx + ((y % m) << bcl) + bl], twf, twfl, (y * r) % ny);
-      cpx<T>* g = colp + (c << bcl) + bl;
+      cpx<T>* g = colp + static_cast<int64_t>(c) * nbp + bl;
       if (acc_lds) {
         cpx<T>* p = acc + it;
         if (n1 == 1) *g = val;
@@ -305,44 +434,150 @@ __device__ void k2r_fwd_task(const KArgs& a, int t, cpx<T>* S) {
 }
 
 // ---------------------------------------------------------------------------
+// Forward class combine (task = plane z, band chunk): column (xi, y = j + m*t)
+// = sum_r w_n1^{-t*r} Z_r[xi][j], the last, length-n1 stage of the
+// decimation-in-time split of the y transform. One (slab, j, band) item per
+// thread: its n1 class partials in, the n1 outputs t out to the columns that
+// exist.
+__device__ __forceinline__ int find_sphere_k3r(const KArgs& a, int t) {
+  int s = 0;
+  while (s + 1 < a.nsph && t >= a.sph[s].k3_end) ++s;
+  return s;
+}
+__device__ __forceinline__ bool codelet_radix(int R) {
+  return R == 1 || R == 2 || R == 3 || R == 4 || R == 5 || R == 6 || R == 8 || R == 9 ||
+         R == 10 || R == 12 || R == 15 || R == 16;
+}
+
+template <typename T>
+__device__ void k3r_task(const KArgs& a, int t) {
+  const int s = find_sphere_k3r(a, t);
+  const SphereDesc d = a.sph[s];
+  const int lt = t - d.k3_start;
+  const int chunk = lt % d.nchunk, z = lt / d.nchunk;
+  const int bcl = a.bcl, bmask = (1 << bcl) - 1;
+  const int b0 = chunk << bcl;
+  const int ny = a.ny, n1 = a.n1, m = a.m;
+  const int nslab = d.nslab, ncol = d.ncol;
+  const int nbp = d.nchunk << bcl;
+  const cpx<T>* __restrict__ zp = reinterpret_cast<const cpx<T>*>(a.col) + d.zp_off +
+                                  static_cast<int64_t>(z) * nslab * ny * nbp + b0;
+  cpx<T>* __restrict__ colp = reinterpret_cast<cpx<T>*>(a.col) + d.col_off +
+                              static_cast<int64_t>(z) * ncol * nbp + b0;
+  const int32_t* __restrict__ cidx = a.colidx + d.colidx_off;
+  const cpx<T>* twf = reinterpret_cast<const cpx<T>*>(a.twf);
+  const cpx<T>* twfl = reinterpret_cast<const cpx<T>*>(a.twf_lo);
+  const float inv_m = 1.0f / static_cast<float>(m);
+  const int items = (nslab * m) << bcl;
+  const bool codelet = codelet_radix(n1);
+  for (int it = threadIdx.x; it < items; it += blockDim.x) {
+    const int bl = it & bmask;
+    const int jx = it >> bcl;
+    const int xi = div_small(jx, m, inv_m);
+    const int j = jx - xi * m;
+    const cpx<T>* __restrict__ src = zp + (static_cast<int64_t>(xi) * ny + j * n1) * nbp + bl;
+    const int32_t* __restrict__ crow = cidx + xi * ny + j;
+    if (codelet) {
+      cpx<T> u[kMaxRadixDev];
+#pragma unroll
+      for (int r = 0; r < kMaxRadixDev; ++r)
+        if (r < n1) u[r] = src[r * nbp];
+      butterfly<-1>(n1, u);
+#pragma unroll
+      for (int q = 0; q < kMaxRadixDev; ++q) {
+        if (q < n1) {
+          const int c = crow[q * m];
+          if (c >= 0) colp[static_cast<int64_t>(c) * nbp + bl] = u[q];
+        }
+      }
+    } else {
+      // class counts without a codelet: direct sums
+      for (int q = 0; q < n1; ++q) {
+        const int c = crow[q * m];
+        if (c < 0) continue;
+        cpx<T> acc = src[0];
+        const int step = m * q;  // w_n1^{q} = w_ny^{m*q}
+        int idx = 0;
+        for (int r = 1; r < n1; ++r) {
+          idx += step;
+          if (idx >= ny) idx -= ny;
+          acc = cadd(acc, twmul<-1>(src[r * nbp], twf, twfl, idx));
+        }
+        colp[static_cast<int64_t>(c) * nbp + bl] = acc;
+      }
+    }
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k3r_kernel(const KArgs a) {
+  if (!a.persistent) {
+    const int t = static_task_g(a.k3_tasks, 1);
+    if (t >= 0) k3r_task<T>(a, t);
+    return;
+  }
+  __shared__ int sh_task;
+  for (;;) {
+    if (threadIdx.x == 0) sh_task = dynamic_task_g(a.counters + 16, a.k3_tasks, 1);
+    __syncthreads();
+    const int t = __builtin_amdgcn_readfirstlane(sh_task);
+    __syncthreads();
+    if (t < 0) break;
+    k3r_task<T>(a, t);
+  }
+}
+
+hipError_t launch_combine(const KArgs& a, bool fp64, int grid, int threads, hipStream_t st) {
+  if (fp64)
+    hipLaunchKernelGGL((k3r_kernel<double>), dim3(grid), dim3(threads), 0, st, a);
+  else
+    hipLaunchKernelGGL((k3r_kernel<float>), dim3(grid), dim3(threads), 0, st, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 template <int S, typename T, int E, int H, bool MF>
 __global__ void __launch_bounds__(256) k1r_kernel(const KArgs a) {
   if (!a.persistent) {
-    const int t = static_task_r(a.k1_tasks);
+    const int t = static_task_g(a.k1_tasks, 1);
     if (t >= 0) k1r_task<S, T, E, H, MF>(a, t);
     return;
   }
   __shared__ int sh_task;
   for (;;) {
-    if (threadIdx.x == 0) sh_task = dynamic_task_r(a.counters, a.k1_tasks);
+    if (threadIdx.x == 0) sh_task = dynamic_task_g(a.counters, a.k1_tasks, 1);
     __syncthreads();
-    const int t = sh_task;
+    const int t = __builtin_amdgcn_readfirstlane(sh_task);
     __syncthreads();
     if (t < 0) break;
     k1r_task<S, T, E, H, MF>(a, t);
   }
 }
 
-template <int S, typename T, int E, int H, bool MF>
+// FC: forward tasks write class partials (compiled apart from the accumulating
+// forward so that neither variant's register allocation limits the other)
+template <int S, typename T, int E, int H, bool MF, bool FC, int M>
 __global__ void __launch_bounds__(512) k2r_kernel(const KArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
   if (!a.persistent) {
-    const int t = static_task_r(a.k2_tasks);
+    const int t = static_task_g(a.k2_tasks, a.g2);
     if (t >= 0) {
-      if constexpr (S > 0) k2r_inv_task<T, E, H, MF>(a, t, lds);
+      if constexpr (S > 0) k2r_inv_task<T, E, H, MF, M>(a, t, lds);
+      else if constexpr (FC) k2r_fwd_cls_task<T, E, H, MF>(a, t, lds);
       else k2r_fwd_task<T, E, H, MF>(a, t, lds);
     }
     return;
   }
   __shared__ int sh_task;
   for (;;) {
-    if (threadIdx.x == 0) sh_task = dynamic_task_r(a.counters + 8, a.k2_tasks);
+    if (threadIdx.x == 0) sh_task = dynamic_task_g(a.counters + 8, a.k2_tasks, a.g2);
     __syncthreads();
-    const int t = sh_task;
+    const int t = __builtin_amdgcn_readfirstlane(sh_task);
     __syncthreads();
     if (t < 0) break;
-    if constexpr (S > 0) k2r_inv_task<T, E, H, MF>(a, t, lds);
+    if constexpr (S > 0) k2r_inv_task<T, E, H, MF, M>(a, t, lds);
+    else if constexpr (FC) k2r_fwd_cls_task<T, E, H, MF>(a, t, lds);
     else k2r_fwd_task<T, E, H, MF>(a, t, lds);
     __syncthreads();
   }
@@ -368,41 +603,76 @@ bool reg_shape_supported(bool fp64, int E, int H) {
   return false;
 }
 
+// Inverse plane kernels with a compile-time class length are compiled for the
+// lines spread over 8 lanes (x lengths 32 .. 160) and m = 8 or 16.
+constexpr bool fold_m_compiled(int H, int m) { return H == 8 && (m == 8 || m == 16); }
+
+template <int S, typename T, int E, int H, bool MF, bool FC, int M>
+static hipError_t launch_k2(const KArgs& a, int grid, int threads, size_t lds, hipStream_t st) {
+  hipLaunchKernelGGL((k2r_kernel<S, T, E, H, MF, FC, M>), dim3(grid), dim3(threads), lds, st, a);
+  return hipGetLastError();
+}
+
+template <int S, typename T, int E, int H, bool MF, bool FC, int M>
+static hipError_t attr_k2(size_t lds) {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(k2r_kernel<S, T, E, H, MF, FC, M>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
 template <int S, typename T, int E, int H, bool MF>
 static hipError_t launch_one(int which, const KArgs& a, int grid, int threads, size_t lds,
-                             hipStream_t st) {
-  if (which == 1)
+                             hipStream_t st, int fold_m) {
+  if (which == 1) {
     hipLaunchKernelGGL((k1r_kernel<S, T, E, H, MF>), dim3(grid), dim3(threads), 0, st, a);
-  else
-    hipLaunchKernelGGL((k2r_kernel<S, T, E, H, MF>), dim3(grid), dim3(threads), lds, st, a);
-  return hipGetLastError();
+    return hipGetLastError();
+  }
+  if constexpr (S < 0) {
+    if (a.fwd_cls) return launch_k2<S, T, E, H, MF, true, 0>(a, grid, threads, lds, st);
+  } else if constexpr (fold_m_compiled(H, 8)) {
+    if (fold_m == 8) return launch_k2<S, T, E, H, MF, false, 8>(a, grid, threads, lds, st);
+    if (fold_m == 16) return launch_k2<S, T, E, H, MF, false, 16>(a, grid, threads, lds, st);
+  }
+  if (fold_m != 0) return hipErrorInvalidValue;
+  return launch_k2<S, T, E, H, MF, false, 0>(a, grid, threads, lds, st);
 }
 
 template <int S, typename T, int E, int H, bool MF>
 static hipError_t attr_one(size_t lds) {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(k2r_kernel<S, T, E, H, MF>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipError_t e = attr_k2<S, T, E, H, MF, false, 0>(lds);
+  if constexpr (S < 0) {
+    if (e == hipSuccess) e = attr_k2<S, T, E, H, MF, true, 0>(lds);
+  } else if constexpr (fold_m_compiled(H, 8)) {
+    if (e == hipSuccess) e = attr_k2<S, T, E, H, MF, false, 8>(lds);
+    if (e == hipSuccess) e = attr_k2<S, T, E, H, MF, false, 16>(lds);
+  }
+  return e;
 }
 
 // the FP32 DFT_16 on the matrix cores is compiled for lines of 16 values per lane
 bool mfma_shape_supported(bool fp64, int E, int H) { return !fp64 && E == 16 && H == 8; }
 
+bool fold_m_supported(int H, int m) { return fold_m_compiled(H, m); }
+
 // which: 1 = column kernel (E, H of the z axis), 2 = plane kernel (E, H of x)
 hipError_t launch_reg(int which, const KArgs& a, bool inverse, bool fp64, int E, int H, int grid,
-                      int threads, size_t lds, hipStream_t st, bool mfma) {
+                      int threads, size_t lds, hipStream_t st, bool mfma, int fold_m) {
   if (mfma) {
     if (fp64 || E != 16 || H != 8) return hipErrorInvalidValue;
-    return inverse ? launch_one<+1, float, 16, 8, true>(which, a, grid, threads, lds, st)
-                   : launch_one<-1, float, 16, 8, true>(which, a, grid, threads, lds, st);
+    return inverse ? launch_one<+1, float, 16, 8, true>(which, a, grid, threads, lds, st, fold_m)
+                   : launch_one<-1, float, 16, 8, true>(which, a, grid, threads, lds, st, fold_m);
   }
-#define FFTB_L64(e, h)                                                                     \
-  if (E == e && H == h)                                                                    \
-    return inverse ? launch_one<+1, double, e, h, false>(which, a, grid, threads, lds, st) \
-                   : launch_one<-1, double, e, h, false>(which, a, grid, threads, lds, st);
-#define FFTB_L32(e, h)                                                                     \
-  if (E == e && H == h)                                                                    \
-    return inverse ? launch_one<+1, float, e, h, false>(which, a, grid, threads, lds, st)  \
-                   : launch_one<-1, float, e, h, false>(which, a, grid, threads, lds, st);
+#define FFTB_L64(e, h)                                                                        \
+  if (E == e && H == h)                                                                       \
+    return inverse ? launch_one<+1, double, e, h, false>(which, a, grid, threads, lds, st,    \
+                                                         fold_m)                             \
+                   : launch_one<-1, double, e, h, false>(which, a, grid, threads, lds, st,    \
+                                                         fold_m);
+#define FFTB_L32(e, h)                                                                        \
+  if (E == e && H == h)                                                                       \
+    return inverse ? launch_one<+1, float, e, h, false>(which, a, grid, threads, lds, st,     \
+                                                        fold_m)                              \
+                   : launch_one<-1, float, e, h, false>(which, a, grid, threads, lds, st,     \
+                                                        fold_m);
   if (fp64) {
     FFTB_REG_SHAPES_F64(FFTB_L64)
   } else {

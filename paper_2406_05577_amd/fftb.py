@@ -89,10 +89,11 @@ class Info_t(C.Structure):
 
 
 class Profile_t(C.Structure):
-    _fields_ = [("launches", C.c_int64 * 4), ("total_ms", C.c_double * 4)]
+    _fields_ = [("launches", C.c_int64 * 5), ("total_ms", C.c_double * 5)]
 
 
-KERNEL_NAMES = ["column_inverse", "plane_inverse", "plane_forward", "column_forward"]
+KERNEL_NAMES = ["column_inverse", "plane_inverse", "plane_forward", "column_forward",
+                "combine_forward"]
 
 
 class FftbError(RuntimeError):

@@ -45,7 +45,8 @@ REG_CASES = [
 ]
 REG_TUNINGS = [None, dict(fwd_acc=2), dict(fwd_acc=1, fwd_band_chunk=2, fwd_splits=3),
                dict(y_classes=4, fwd_y_classes=8), dict(band_chunk=2, col_tile=3, fwd_band_chunk=4),
-               dict(fwd_splits=5, threads=512)]
+               dict(fwd_splits=5, threads=512), dict(fwd_acc=3, y_classes=8, threads=512),
+               dict(fwd_acc=3, fwd_band_chunk=2, fwd_col_tile=5)]
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
@@ -105,6 +106,32 @@ def test_forward_not_band_limited(dtype):
     g = [synth.random_grid(np.random.default_rng(99), dims, nb)]
     e = check_workload(w, dtype, grid_in=g)
     assert e[1] <= TOL[dtype], e
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("holes", ["columns", "coeffs"])
+def test_map_with_holes(dtype, holes):
+    """Maps that are not a convex cutoff sphere: whole columns removed (slabs
+    whose y values form more than two runs, which takes the generic fold), or
+    single coefficients removed at random (columns with gaps along z)."""
+    dims, semi = (64, 32, 48), (20, 10, 15)
+    m, lin = synth.sphere_map(dims, semi, (0.2, -0.3, 0.1))
+    nx, ny, _ = dims
+    x, y = lin % nx, (lin // nx) % ny
+    if holes == "columns":
+        keep = ((x * 7 + y * 3) % 5) != 0
+    else:
+        keep = np.random.default_rng(5).random(lin.shape[0]) > 0.3
+    lin = np.ascontiguousarray(lin[keep])
+    rng = np.random.default_rng(11)
+    nb = 12
+    c = synth.draw_coefficients(rng, lin.shape[0], nb)
+    dt = np.complex128 if dtype == "c128" else np.complex64
+    w = synth.Workload(name="holes", dims=dims, spheres=[synth.Sphere(m=m[keep], lin=lin, kpt=(0, 0, 0), nbands=nb)],
+                       coeffs=[c.astype(dt)], dtype=np.dtype(dt), seed=11)
+    for tun in (None, dict(y_classes=4, fwd_y_classes=2), dict(y_classes=2, band_chunk=4)):
+        e = check_workload(w, dtype, tuning=tun)
+        assert max(e) <= TOL[dtype], (tun, e)
 
 
 def test_c1_full():
