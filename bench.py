@@ -47,7 +47,7 @@ DESCR = {
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("kernels.hip", "kernels_reg.hip", "device_common.hpp", "api.cpp", "plan.cpp"):
+    for f in ("kernels.hip", "kernels_reg.hip", "device_common.hpp", "kargs.hpp", "api.cpp", "plan.cpp"):
         with open(os.path.join(ROOT, "paper_2406_05577_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -66,6 +66,69 @@ def traffic_from_profiles(workload: str, src_hash: str):
     except (OSError, ValueError):
         pass
     return None
+
+
+def _counter_rows(d: str):
+    """Rows of a rocprofv3 --pmc CSV (the *_counter_collection.csv under d)."""
+    import csv
+    import glob
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no counter_collection.csv under {d}")
+    with open(files[0]) as f:
+        return list(csv.DictReader(f))
+
+
+def _per_kernel_kib(d: str, counter: str):
+    """Mean counter value (KiB) per dispatch for each kernel name."""
+    acc = {}
+    for r in _counter_rows(d):
+        if r["Counter_Name"] != counter:
+            continue
+        name = r["Kernel_Name"].split("(")[0].replace("void ", "")
+        acc.setdefault(name, []).append(float(r["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in acc.items()}
+
+
+def summarize_counters(args):
+    """Turn FETCH_SIZE / WRITE_SIZE passes (rocprofv3 --pmc CSV) of the bench
+    and of a plain 1 GiB copy into per-launch HBM bytes of the plane kernels:
+    each counter is scaled by (bytes the copy moves) / (what it reads for the
+    copy). Writes profiles/traffic.json[workload] and prints a summary."""
+    fetch_dir, write_dir, copy_fetch_dir, copy_write_dir = args.summarize_counters
+    gib_kib = float(1 << 20)
+    cf = _per_kernel_kib(copy_fetch_dir, "FETCH_SIZE")
+    cw = _per_kernel_kib(copy_write_dir, "WRITE_SIZE")
+    copy_name = max(cf, key=lambda k: cf[k])
+    f_fetch = gib_kib / cf[copy_name]
+    f_write = gib_kib / cw[max(cw, key=lambda k: cw[k])]
+    fe = _per_kernel_kib(fetch_dir, "FETCH_SIZE")
+    wr = _per_kernel_kib(write_dir, "WRITE_SIZE")
+    rows = []
+    plane = []
+    for k in sorted(set(fe) | set(wr)):
+        if "fftb" not in k:
+            continue
+        byts = (fe.get(k, 0.0) * f_fetch + wr.get(k, 0.0) * f_write) * 1024.0
+        rows.append((k, fe.get(k, 0.0), wr.get(k, 0.0), byts))
+        if "k2" in k:
+            plane.append(byts)
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        d = {}
+    d[args.workload] = {"plane_bytes_per_launch": sum(plane) / len(plane) if plane else None,
+                        "fetch_factor": f_fetch, "write_factor": f_write,
+                        "source_hash": kernel_source_hash()}
+    with open(path, "w") as f:
+        json.dump(d, f, indent=1, sort_keys=True)
+    print(f"calibration: {copy_name} 1 GiB copy, FETCH_SIZE x{f_fetch:.3f}, WRITE_SIZE x{f_write:.3f}")
+    print("| kernel | FETCH_SIZE KiB/dispatch | WRITE_SIZE KiB/dispatch | HBM bytes/dispatch (calibrated) |")
+    print("|---|---|---|---|")
+    for k, a, w, byts in rows:
+        print(f"| `{k}` | {a:.0f} | {w:.0f} | {byts / 1e9:.3f} GB |")
 
 
 def cpu_baseline(w_name: str, sample_bands: int):
@@ -108,7 +171,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="skip per-kernel event timing (graph replays never record it)")
+    ap.add_argument("--summarize-counters", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
+                    help="rocprofv3 --pmc output folders: write profiles/traffic.json for --workload")
     args = ap.parse_args()
+    if args.summarize_counters:
+        summarize_counters(args)
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "

@@ -70,7 +70,7 @@ struct DirCfg {
   std::vector<int32_t> splits;      // per sphere nsplit+1 slab boundaries
   int sx = 0;
   size_t lds1 = 0, lds2 = 0;
-  int lds_P = 0, lds_X0 = 0, lds_X1 = 0, lds_acc = 0;
+  int lds_P = 0, lds_X0 = 0, lds_X1 = 0, lds_acc = 0, lds_tab = 0;
   AxisPlan ay;                      // y plan of length m
   std::vector<SphereDesc> desc;
   int k1_tasks = 0, k2_tasks = 0, k3_tasks = 0;
@@ -100,8 +100,13 @@ struct fftb_plan_s {
   // device memory
   std::vector<DevBuf> bufs;
   int32_t *d_gidx = nullptr, *d_colidx = nullptr, *d_colxi = nullptr, *d_coly = nullptr,
-          *d_xinv = nullptr, *d_slabstart = nullptr, *d_slabruns = nullptr, *d_slaborder = nullptr;
-  bool two_runs = true;  // every slab of every sphere is at most two runs of y
+          *d_xinv = nullptr, *d_slabstart = nullptr, *d_colslot = nullptr, *d_slabblk = nullptr,
+          *d_slabnblk = nullptr, *d_slaborder = nullptr;
+  // column scratch slots: with pad_m > 0 every slab's columns sit in zero-padded
+  // blocks of pad_m consecutive y (the inverse fold reads whole blocks)
+  int pad_m = 0;
+  std::vector<int32_t> col_slot, slab_blk, slab_nblk, colidx_slot;  // concatenated over spheres
+  std::vector<int32_t> npcol;                            // per sphere
   void *d_twx = nullptr, *d_twz = nullptr, *d_twf = nullptr;
   void *d_twx_lo = nullptr, *d_twz_lo = nullptr, *d_twf_lo = nullptr;
   void *d_rootx = nullptr, *d_rootx_lo = nullptr, *d_rootz = nullptr, *d_rootz_lo = nullptr;
@@ -206,6 +211,30 @@ size_t plane_lds_reg(const fftb_plan_s& P, int m, int bc, bool acc, int& sx, int
   return static_cast<size_t>(S + A) * es_of(P.dtype);
 }
 
+// Slots of the padded layout stay below 2^21 (they are packed with the block index).
+bool fold_slots_fit(const fftb_plan_s& P, int M) {
+  for (auto& s : P.sph) {
+    int64_t slots = 0;
+    for (int xi = 0; xi < s.nslab; ++xi) {
+      int cur = -1;
+      for (int c = s.slabstart[xi]; c < s.slabstart[xi + 1]; ++c)
+        if (s.col_y[c] / M != cur) {
+          cur = s.col_y[c] / M;
+          slots += M;
+        }
+    }
+    if (slots >= (int64_t{1} << 21)) return false;
+  }
+  return true;
+}
+
+// LDS of the inverse fold's staged tables: per slab n1 block entries and a
+// count, then n1 roots (hi and lo) of the class.
+size_t fold_table_bytes(const fftb_plan_s& P, int n1) {
+  const size_t ints = static_cast<size_t>(P.max_nslab) * n1 + ((P.max_nslab + 3) & ~3);
+  return ints * 4 + static_cast<size_t>(2 * n1) * es_of(P.dtype);
+}
+
 // Cut a sphere's slabs into Q contiguous ranges with about equal column counts.
 void split_slabs(const SphereTables& sp, int Q, std::vector<int32_t>& cuts) {
   cuts.assign(Q + 1, sp.nslab);
@@ -288,12 +317,15 @@ fftb_status choose_dir(fftb_plan_s& P, int d, const fftb_dir_tuning& t) {
         if (want_fold_m && !fold_m_supported(h2, m)) continue;
         if (want_codelet && !single_codelet(c)) continue;
         int sx, oa;
-        const size_t b = plane_lds_reg(P, m, bc, false, sx, oa);
+        size_t b = plane_lds_reg(P, m, bc, false, sx, oa);
+        const size_t tab_at = (b + 15) & ~size_t{15};
+        if (want_fold_m) b = tab_at + fold_table_bytes(P, c);
         if (b > cap) continue;
         D.reg2 = true;
         D.n1 = c;
         D.m = m;
         D.lds2 = b;
+        D.lds_tab = static_cast<int>(tab_at);
         D.sx = sx;
         D.class_par = true;
         return;
@@ -305,9 +337,14 @@ fftb_status choose_dir(fftb_plan_s& P, int d, const fftb_dir_tuning& t) {
   if (t.path != 1 && reg_shape(P.nx, fp64, e2, h2)) {
     if (inverse) {
       // prefer a class length with a compiled register fold
-      if (P.two_runs) pick_classes(true, false);
+      pick_classes(true, false);
       if (!D.reg2) pick_classes(false, false);
-      D.fold_m = D.reg2 && P.two_runs && fold_m_supported(h2, D.m) ? D.m : 0;
+      D.fold_m = D.reg2 && fold_m_supported(h2, D.m) && D.n1 <= 1024 && fold_slots_fit(P, D.m)
+                     ? D.m : 0;
+      if (D.reg2 && !D.fold_m) {
+        // the generic fold needs no staged tables
+        pick_classes(false, false);
+      }
     } else if ((t.acc == 0 || t.acc == 3) && t.splits <= 1 && D.reg1) {
       // class partials combined by a separate kernel: no accumulators
       pick_classes(false, true);
@@ -450,6 +487,51 @@ void fill_axis(const AxisPlan& a, AxisDev& d) {
   }
 }
 
+// Column scratch slots. With M = pad_m > 0, slab xi's columns occupy blocks of
+// M slots, one block per M-aligned run of y (y = tb*M .. tb*M + M - 1) that
+// holds a column, in ascending y; slots of absent y stay zero (the scratch is
+// cleared once at plan creation and no kernel writes them). slab_blk gives the
+// per slab the list of its blocks as (first slot << 10 | tb) and their count.
+// M = 0: slot = column.
+void build_slots(fftb_plan_s& P) {
+  const int M = P.pad_m;
+  const int nblk = M > 0 ? P.ny / M : 0;
+  P.col_slot.clear();
+  P.slab_blk.clear();
+  P.slab_nblk.clear();
+  P.colidx_slot.clear();
+  P.npcol.clear();
+  for (auto& s : P.sph) {
+    std::vector<int32_t> slot(s.ncol);
+    int next = 0;
+    if (M > 0) {
+      // per slab: the blocks holding columns, ascending, as (first slot << 10 | tb)
+      std::vector<int32_t> list(static_cast<size_t>(s.nslab) * nblk, -1);
+      for (int xi = 0; xi < s.nslab; ++xi) {
+        int n = 0, cur_tb = -1, cur_slot = 0;
+        for (int c = s.slabstart[xi]; c < s.slabstart[xi + 1]; ++c) {
+          const int tb = s.col_y[c] / M;
+          if (tb != cur_tb) {
+            cur_tb = tb;
+            cur_slot = next;
+            next += M;
+            list[static_cast<size_t>(xi) * nblk + n++] = (cur_slot << 10) | tb;
+          }
+          slot[c] = cur_slot + (s.col_y[c] - tb * M);
+        }
+        P.slab_nblk.push_back(n);
+      }
+      P.slab_blk.insert(P.slab_blk.end(), list.begin(), list.end());
+    } else {
+      for (int c = 0; c < s.ncol; ++c) slot[c] = c;
+      next = s.ncol;
+    }
+    P.npcol.push_back(next);
+    P.col_slot.insert(P.col_slot.end(), slot.begin(), slot.end());
+    for (int32_t c : s.colidx) P.colidx_slot.push_back(c >= 0 ? slot[c] : -1);
+  }
+}
+
 // Per-sphere descriptors and task ranges of one direction.
 void build_descs(fftb_plan_s& P, DirCfg& D) {
   const int bc = D.bc;
@@ -472,6 +554,7 @@ void build_descs(fftb_plan_s& P, DirCfg& D) {
     d.slab_off = so;
     d.sl_off = sl;
     d.ncol = s.ncol;
+    d.npcol = P.npcol[&s - P.sph.data()];
     d.nslab = s.nslab;
     d.nb = s.nb;
     d.nchunk = (s.nb + bc - 1) / bc;
@@ -491,7 +574,7 @@ void build_descs(fftb_plan_s& P, DirCfg& D) {
     d.zp_off = zoff;  // relative to the end of the column region, fixed up below
     soff += s.ns * s.nb;
     goff += N * s.nb;
-    coff += static_cast<int64_t>(d.nchunk) * bc * P.nz * s.ncol;
+    coff += static_cast<int64_t>(d.nchunk) * bc * P.nz * d.npcol;
     if (D.fwd_cls) zoff += static_cast<int64_t>(d.nchunk) * bc * P.nz * s.nslab * P.ny;
     gi += s.ncol * P.nz;
     ci += s.nslab * P.ny;
@@ -559,12 +642,10 @@ fftb_status device_setup(fftb_plan_s& P, hipStream_t st) {
   if (e != hipSuccess)
     return fail(FFTB_ERR_HIP, std::string("hipGetDeviceProperties: ") + hipGetErrorString(e));
   P.num_cus = prop.multiProcessorCount;
-  std::vector<int32_t> gidx, colidx, colxi, coly, xinv, slabstart, slabruns, slaborder;
+  std::vector<int32_t> gidx, colxi, coly, xinv, slabstart, slaborder;
   for (auto& s : P.sph) {
-    slabruns.insert(slabruns.end(), s.slab_runs.begin(), s.slab_runs.end());
     slaborder.insert(slaborder.end(), s.slab_order.begin(), s.slab_order.end());
     gidx.insert(gidx.end(), s.gidx.begin(), s.gidx.end());
-    colidx.insert(colidx.end(), s.colidx.begin(), s.colidx.end());
     colxi.insert(colxi.end(), s.col_xi.begin(), s.col_xi.end());
     coly.insert(coly.end(), s.col_y.begin(), s.col_y.end());
     xinv.insert(xinv.end(), s.xinv.begin(), s.xinv.end());
@@ -581,7 +662,7 @@ fftb_status device_setup(fftb_plan_s& P, hipStream_t st) {
   }
   if ((s = upload(P, gidx, &p, st)) != FFTB_OK) return s;
   P.d_gidx = static_cast<int32_t*>(p);
-  if ((s = upload(P, colidx, &p, st)) != FFTB_OK) return s;
+  if ((s = upload(P, P.colidx_slot, &p, st)) != FFTB_OK) return s;
   P.d_colidx = static_cast<int32_t*>(p);
   if ((s = upload(P, colxi, &p, st)) != FFTB_OK) return s;
   P.d_colxi = static_cast<int32_t*>(p);
@@ -591,8 +672,12 @@ fftb_status device_setup(fftb_plan_s& P, hipStream_t st) {
   P.d_xinv = static_cast<int32_t*>(p);
   if ((s = upload(P, slabstart, &p, st)) != FFTB_OK) return s;
   P.d_slabstart = static_cast<int32_t*>(p);
-  if ((s = upload(P, slabruns, &p, st)) != FFTB_OK) return s;
-  P.d_slabruns = static_cast<int32_t*>(p);
+  if ((s = upload(P, P.col_slot, &p, st)) != FFTB_OK) return s;
+  P.d_colslot = static_cast<int32_t*>(p);
+  if ((s = upload(P, P.slab_blk, &p, st)) != FFTB_OK) return s;
+  P.d_slabblk = static_cast<int32_t*>(p);
+  if ((s = upload(P, P.slab_nblk, &p, st)) != FFTB_OK) return s;
+  P.d_slabnblk = static_cast<int32_t*>(p);
   if ((s = upload(P, slaborder, &p, st)) != FFTB_OK) return s;
   P.d_slaborder = static_cast<int32_t*>(p);
   if ((s = upload_tw(P, axis_twiddles(P.ax), &P.d_twx, &P.d_twx_lo, st)) != FFTB_OK) return s;
@@ -600,9 +685,12 @@ fftb_status device_setup(fftb_plan_s& P, hipStream_t st) {
   if ((s = upload_tw(P, root_table(P.ny), &P.d_twf, &P.d_twf_lo, st)) != FFTB_OK) return s;
   if ((s = upload_tw(P, root_table(P.nx), &P.d_rootx, &P.d_rootx_lo, st)) != FFTB_OK) return s;
   if ((s = upload_tw(P, root_table(P.nz), &P.d_rootz, &P.d_rootz_lo, st)) != FFTB_OK) return s;
-  const int64_t col_elems = std::max(P.dir[0].col_elems, P.dir[1].col_elems);
+  const int64_t col_elems = P.dir[0].col_elems + P.dir[1].col_elems;
   if ((s = dev_alloc(P, static_cast<size_t>(col_elems) * es_of(P.dtype), &P.d_col)) != FFTB_OK)
     return s;
+  // padding slots of the column scratch must read as zero
+  e = hipMemsetAsync(P.d_col, 0, static_cast<size_t>(col_elems) * es_of(P.dtype), st);
+  if (e != hipSuccess) return fail(FFTB_ERR_HIP, std::string("hipMemsetAsync: ") + hipGetErrorString(e));
   if ((s = dev_alloc(P, 24 * sizeof(unsigned int), &p)) != FFTB_OK) return s;
   P.d_counters = static_cast<unsigned int*>(p);
   e = hipMemsetAsync(P.d_counters, 0, 24 * sizeof(unsigned int), st);
@@ -666,7 +754,10 @@ KArgs make_args(const fftb_plan_s& P, const DirCfg& D, const void* in, void* out
   a.col_y = P.d_coly;
   a.xinv = P.d_xinv;
   a.slabstart = P.d_slabstart;
-  a.slab_runs = P.d_slabruns;
+  a.col_slot = P.d_colslot;
+  a.slab_blk = P.d_slabblk;
+  a.slab_nblk = P.d_slabnblk;
+  a.lds_tab = D.lds_tab;
   a.slab_order = P.d_slaborder;
   a.twx = P.d_twx;
   a.twy = D.d_twy;
@@ -1054,7 +1145,6 @@ fftb_status fftb_plan_create(fftb_plan* out, const int32_t dims[3], const fftb_s
         return fail(FFTB_ERR_INVALID, buf + err);
       }
       for (int k = 0; k < 3; ++k) P->sph[s].kpt[k] = spheres[s].kpt[k];
-      P->two_runs = P->two_runs && P->sph[s].two_runs;
       P->max_ncol = std::max(P->max_ncol, P->sph[s].ncol);
       P->max_nslab = std::max(P->max_nslab, P->sph[s].nslab);
       P->total_columns += P->sph[s].ncol;
@@ -1072,7 +1162,16 @@ fftb_status fftb_plan_create(fftb_plan* out, const int32_t dims[3], const fftb_s
     for (int d = 0; d < 2; ++d) {
       fftb_status st = choose_dir(*P, d, d == 0 ? t.inv : t.fwd);
       if (st != FFTB_OK) return st;
-      build_descs(*P, P->dir[d]);
+    }
+    P->pad_m = P->dir[0].fold_m;
+    build_slots(*P);
+    for (int d = 0; d < 2; ++d) build_descs(*P, P->dir[d]);
+    // the scratch holds the inverse's columns first, then the forward's columns
+    // and class partials: the inverse fold relies on its zero padding slots,
+    // which a forward with another band stride would otherwise overwrite
+    for (auto& dd : P->dir[1].desc) {
+      dd.col_off += P->dir[0].col_elems;
+      dd.zp_off += P->dir[0].col_elems;
     }
     for (int d = 0; d < 2; ++d) {
       const DirCfg& D = P->dir[d];

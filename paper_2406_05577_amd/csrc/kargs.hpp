@@ -23,10 +23,11 @@ struct SphereDesc {
   int64_t col_off;     // first element of this sphere's column scratch
   int64_t zp_off;      // first element of this sphere's forward class partials
   int32_t gidx_off;    // ncol*nz table: coefficient index of (column, z) or -1
-  int32_t colidx_off;  // nslab*ny table: column index of (slab, y) or -1
-  int32_t colmeta_off; // per-column slab index and y
+  int32_t colidx_off;  // nslab*ny table: scratch slot of the column at (slab, y) or -1
+  int32_t colmeta_off; // per-column slab index, y and scratch slot
   int32_t xinv_off;    // nx table: slab index of x or -1
   int32_t ncol;
+  int32_t npcol;       // scratch slots per plane (>= ncol: zero-padded y blocks)
   int32_t nslab;
   int32_t nb;
   int32_t nchunk;      // ceil(nb / band_chunk)
@@ -49,6 +50,7 @@ struct KArgs {
   int persistent;
   int lds_P, lds_X0, lds_X1;  // element offsets of LDS regions (S starts at 0)
   int lds_acc;       // element offset of the forward column accumulators
+  int lds_tab;       // byte offset of the inverse fold's block lists and roots
   int acc_lds;       // forward plane kernel accumulates columns in LDS
   int sx;            // element stride between slab lines of the class slab
   int nsplit;        // forward plane tasks per (plane, chunk): slab ranges with their columns
@@ -63,7 +65,10 @@ struct KArgs {
   const int32_t* xinv;
   const int32_t* slabstart;
   const int32_t* splits;
-  const int32_t* slab_runs;  // 4 per slab: y runs [a0, a1), [b0, b1) in column order
+  const int32_t* col_slot;   // per column: scratch slot
+  const int32_t* slab_blk;   // per sphere nslab*n1 (inverse n1): the slab's y blocks that hold
+                             // columns, as (first slot << 10 | block index), ascending
+  const int32_t* slab_nblk;  // per slab: number of such blocks
   const int32_t* slab_order; // per sphere: slab indices by descending column count
   const void* twx;      // forward-sign twiddles (double pairs, or FP32 hi)
   const void* twy;

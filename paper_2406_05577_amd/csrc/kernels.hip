@@ -123,7 +123,8 @@ __device__ void k1_task(const KArgs& a, int t, cpx<T>* lds) {
   const int nl = min(a.lc, d.ncol - c0);
   const int bcl = a.bcl, bc = 1 << bcl;
   const int b0 = chunk << bcl;
-  const int nz = a.nz, nb = d.nb, ncol = d.ncol;
+  const int nz = a.nz, nb = d.nb, npcol = d.npcol;
+  const int32_t* __restrict__ cslot = a.col_slot + d.colmeta_off;
   const int32_t* __restrict__ gidx = a.gidx + d.gidx_off;
   cpx<T>* colbuf = reinterpret_cast<cpx<T>*>(a.col) + d.col_off;
   const cpx<T>* tw = reinterpret_cast<const cpx<T>*>(a.twz);
@@ -140,14 +141,14 @@ __device__ void k1_task(const KArgs& a, int t, cpx<T>* lds) {
       return cpx<T>{0, 0};
     };
     auto gdst = [=](int line, int z, int bl, cpx<T> v) {
-      colbuf[(static_cast<int64_t>(z) * ncol + c0 + line) * nbp + b0 + bl] = v;
+      colbuf[(static_cast<int64_t>(z) * npcol + cslot[c0 + line]) * nbp + b0 + bl] = v;
     };
     axis_run<S, T>(a.az, nl, tw, twlo, bcl, b_0, b_1, gsrc, gdst);
   } else {
     cpx<T>* __restrict__ out = reinterpret_cast<cpx<T>*>(a.out) + d.sph_off;
     const T sc = static_cast<T>(a.scale);
     auto gsrc = [=](int line, int z, int bl) -> cpx<T> {
-      return colbuf[(static_cast<int64_t>(z) * ncol + c0 + line) * nbp + b0 + bl];
+      return colbuf[(static_cast<int64_t>(z) * npcol + cslot[c0 + line]) * nbp + b0 + bl];
     };
     auto gdst = [=](int line, int z, int bl, cpx<T> v) {
       const int g = gidx[(c0 + line) * nz + z];
@@ -176,13 +177,15 @@ __device__ void k2_task(const KArgs& a, int t, cpx<T>* lds) {
   const int bmask = (1 << bcl) - 1;
   const int b0 = chunk << bcl;
   const int nx = a.nx, ny = a.ny, n1 = a.n1, m = a.m;
-  const int nb = d.nb, ncol = d.ncol, nslab = d.nslab;
-  const int32_t* __restrict__ colidx = a.colidx + d.colidx_off;
+  const int nb = d.nb, ncol = d.ncol, nslab = d.nslab, npcol = d.npcol;
+  const int32_t* __restrict__ colidx = a.colidx + d.colidx_off;  // (slab, y) -> slot
+  const int32_t* __restrict__ cslot = a.col_slot + d.colmeta_off;
   const int32_t* __restrict__ xinv = a.xinv + d.xinv_off;
   const int32_t* __restrict__ cxi = a.col_xi + d.colmeta_off;
   const int32_t* __restrict__ cy = a.col_y + d.colmeta_off;
   const int64_t nbp = d.nchunk << bcl;
-  cpx<T>* colp = reinterpret_cast<cpx<T>*>(a.col) + d.col_off + static_cast<int64_t>(z) * ncol * nbp + b0;
+  cpx<T>* colp =
+      reinterpret_cast<cpx<T>*>(a.col) + d.col_off + static_cast<int64_t>(z) * npcol * nbp + b0;
   const cpx<T>* twx = reinterpret_cast<const cpx<T>*>(a.twx);
   const cpx<T>* twxl = reinterpret_cast<const cpx<T>*>(a.twx_lo);
   const cpx<T>* twy = reinterpret_cast<const cpx<T>*>(a.twy);
@@ -288,7 +291,7 @@ __device__ void k2_task(const KArgs& a, int t, cpx<T>* lds) {
         const int xi = cxi[c], y = cy[c];
         const int ym = y % m;
         cpx<T> v = twmul<S>(Yb[((xi * m + ym) << bcl) + bl], twf, twfl, (y * r) % ny);
-        cpx<T>* p = colp + (static_cast<int64_t>(c) * nbp + bl);
+        cpx<T>* p = colp + (static_cast<int64_t>(cslot[c]) * nbp + bl);
         if (r > 0) v = cadd(v, *p);
         *p = v;
       }

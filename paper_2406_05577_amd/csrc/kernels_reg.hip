@@ -62,9 +62,10 @@ __device__ void k1r_task(const KArgs& a, int t) {
   const int nl = min(a.lc, d.ncol - c0);
   const int bcl = a.bcl, bmask = (1 << bcl) - 1;
   const int b0 = chunk << bcl;
-  const int nz = a.nz, nb = d.nb, ncol = d.ncol;
+  const int nz = a.nz, nb = d.nb, npcol = d.npcol;
+  const int32_t* __restrict__ cslot = a.col_slot + d.colmeta_off;
   const int32_t* __restrict__ gidx = a.gidx + d.gidx_off;
-  // column scratch: one padded band vector (nbp values) per (z, column)
+  // column scratch: one padded band vector (nbp values) per (z, column slot)
   const int nbp = d.nchunk << bcl;
   cpx<T>* __restrict__ colbuf = reinterpret_cast<cpx<T>*>(a.col) + d.col_off + b0;
   const cpx<T>* rootz = reinterpret_cast<const cpx<T>*>(a.rootz);
@@ -79,6 +80,7 @@ __device__ void k1r_task(const KArgs& a, int t) {
     const int rest = iv / H;
     const int bl = rest & bmask;
     const int c = c0 + (rest >> bcl);
+    const int slot = cslot[c];
     const int b = b0 + bl;
     cpx<T> v[E];
     if constexpr (S > 0) {
@@ -91,7 +93,7 @@ __device__ void k1r_task(const KArgs& a, int t) {
     } else {
 #pragma unroll
       for (int j = 0; j < E; ++j)
-        v[j] = valid ? colbuf[(static_cast<int64_t>(h + H * j) * ncol + c) * nbp + bl]
+        v[j] = valid ? colbuf[(static_cast<int64_t>(h + H * j) * npcol + slot) * nbp + bl]
                      : cpx<T>{0, 0};
     }
     line_fft<E, H, S, T, MF>(v, h, rootz, rootz_lo);
@@ -100,7 +102,7 @@ __device__ void k1r_task(const KArgs& a, int t) {
     if constexpr (S > 0) {
 #pragma unroll
       for (int k = 0; k < E; ++k)
-        colbuf[(static_cast<int64_t>(k + E * q) * ncol + c) * nbp + bl] = v[k];
+        colbuf[(static_cast<int64_t>(k + E * q) * npcol + slot) * nbp + bl] = v[k];
     } else {
       cpx<T>* __restrict__ out = reinterpret_cast<cpx<T>*>(a.out) + d.sph_off;
       const T sc = static_cast<T>(a.scale);
@@ -114,18 +116,10 @@ __device__ void k1r_task(const KArgs& a, int t) {
 }
 
 // ---------------------------------------------------------------------------
-// Column index of y in a slab whose sorted y values are the runs [a0, a1) and
-// [b0, b1) starting at column cs, or -1.
-__device__ __forceinline__ int run_col(int y, int cs, int a0, int a1, int b0, int b1) {
-  const unsigned da = static_cast<unsigned>(y - a0);
-  if (da < static_cast<unsigned>(a1 - a0)) return cs + static_cast<int>(da);
-  const unsigned db = static_cast<unsigned>(y - b0);
-  return db < static_cast<unsigned>(b1 - b0) ? cs + (a1 - a0) + static_cast<int>(db) : -1;
-}
-
-// M > 0: the class length m = M is a compile-time constant and every slab's
-// columns form at most two runs of consecutive y; one thread folds and
-// transforms a whole (slab, band) line in registers. M == 0: generic fold.
+// M > 0: the class length m = M is a compile-time constant and the column
+// slots are laid out in zero-padded blocks of M consecutive y per slab; one
+// thread folds and transforms a whole (slab, band) line in registers.
+// M == 0: generic fold.
 template <typename T, int E, int H, bool MF, int M>
 __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S) {
   constexpr int L = log2_const<H>();
@@ -139,11 +133,11 @@ __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S) {
   const int bcl = a.bcl, bmask = (1 << bcl) - 1;
   const int b0 = chunk << bcl;
   const int nx = a.nx, ny = a.ny, sx = a.sx;
-  const int nb = d.nb, ncol = d.ncol, nslab = d.nslab;
+  const int nb = d.nb, npcol = d.npcol, nslab = d.nslab;
   const int32_t* __restrict__ xinv = a.xinv + d.xinv_off;
   const int nbp = d.nchunk << bcl;
   const cpx<T>* __restrict__ colp = reinterpret_cast<const cpx<T>*>(a.col) + d.col_off +
-                                    static_cast<int64_t>(z) * ncol * nbp + b0;
+                                    static_cast<int64_t>(z) * npcol * nbp + b0;
   const cpx<T>* twf = reinterpret_cast<const cpx<T>*>(a.twf);
   const cpx<T>* twfl = reinterpret_cast<const cpx<T>*>(a.twf_lo);
   const cpx<T>* rootx = reinterpret_cast<const cpx<T>*>(a.rootx);
@@ -151,43 +145,76 @@ __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S) {
 
   if constexpr (M > 0) {
     // per (slab, band) line, heaviest slabs first: for each block tb of M
-    // consecutive y (y = k + M*tb) that meets the slab, u[k] += col(y) * w_n1^{+tb*r};
-    // then u[k] *= w_ny^{+k*r} and the length-M IFFT, written once to S
-    const int32_t* __restrict__ runs = a.slab_runs + 4 * d.sl_off;
+    // consecutive y (y = k + M*tb) holding a column of the slab, u[k] +=
+    // col(y) * w_n1^{+tb*r} (absent columns are zero slots); then u[k] *=
+    // w_ny^{+k*r} and the length-M IFFT, written once to S. The slab's block
+    // list (slot << 10 | tb) and the roots w_n1^{+tb*r} are staged in LDS.
+    int32_t* tl = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(S) + a.lds_tab);
+    int32_t* tn = tl + nslab * n1;
+    cpx<T>* troot = reinterpret_cast<cpx<T>*>(tn + ((nslab + 3) & ~3));
+    {
+      const int32_t* __restrict__ blk = a.slab_blk + d.sl_off * n1;
+      const int32_t* __restrict__ nblk = a.slab_nblk + d.sl_off;
+      for (int i = threadIdx.x; i < nslab * n1; i += blockDim.x) tl[i] = blk[i];
+      for (int i = threadIdx.x; i < nslab; i += blockDim.x) tn[i] = nblk[i];
+      for (int tb = threadIdx.x; tb < n1; tb += blockDim.x) {
+        const int idx = M * ((tb * r) % n1);  // w_n1^{tb*r} = w_ny^{M*((tb*r) mod n1)}
+        cpx<T> w = twf[idx];
+        w.im = -w.im;
+        troot[2 * tb] = w;
+        if constexpr (std::is_same<T, float>::value) {
+          cpx<T> wl = twfl[idx];
+          wl.im = -wl.im;
+          troot[2 * tb + 1] = wl;
+        }
+      }
+    }
+    __syncthreads();
+    // two blocks per round trip when their values fit the register budget
+    constexpr bool kPair = M * sizeof(T) <= 64;
     const int32_t* __restrict__ order = a.slab_order + d.sl_off;
-    const int32_t* __restrict__ sst = a.slabstart + d.slab_off;
-    const int mr = M * r;  // w_n1^{tb*r} = w_ny^{M*tb*r}
     const int nlines = nslab << bcl;
     for (int it = threadIdx.x; it < nlines; it += blockDim.x) {
       const int bl = it & bmask;
       const int xi = order[it >> bcl];
-      const int cs = sst[xi];
-      const int a0 = runs[4 * xi], a1 = runs[4 * xi + 1];
-      const int b0 = runs[4 * xi + 2], b1 = runs[4 * xi + 3];
+      const int nh = tn[xi];
+      const int32_t* lst = tl + xi * n1;
       cpx<T> u[M];
 #pragma unroll
       for (int k = 0; k < M; ++k) u[k] = cpx<T>{0, 0};
-      int idx = 0;
-      for (int tb = 0; tb < n1; ++tb, idx = (idx + mr >= ny) ? idx + mr - ny : idx + mr) {
-        const int y0 = tb * M;
-        const bool hit = (y0 < a1 && y0 + M > a0) || (y0 < b1 && y0 + M > b0);
-        if (!hit) continue;
-        cpx<T> v[M];
-#pragma unroll
-        for (int k = 0; k < M; ++k) {
-          const int c = run_col(y0 + k, cs, a0, a1, b0, b1);
-          v[k] = c >= 0 ? colp[static_cast<int64_t>(c) * nbp + bl] : cpx<T>{0, 0};
-        }
-        cpx<T> w = twf[idx];
-        w.im = -w.im;
+      auto accumulate = [&](const cpx<T>* v, int tb, bool use) {
+        cpx<T> w = troot[2 * tb];
+        if (!use) w = cpx<T>{0, 0};
         if constexpr (std::is_same<T, float>::value) {
-          cpx<T> wl = twfl[idx];
-          wl.im = -wl.im;
+          cpx<T> wl = troot[2 * tb + 1];
+          if (!use) wl = cpx<T>{0, 0};
 #pragma unroll
           for (int k = 0; k < M; ++k) u[k] = cadd(u[k], cadd(cmul(v[k], w), cmul(v[k], wl)));
         } else {
 #pragma unroll
           for (int k = 0; k < M; ++k) u[k] = cadd(u[k], cmul(v[k], w));
+        }
+      };
+      for (int i = 0; i < nh; i += (kPair ? 2 : 1)) {
+        const int e0 = lst[i];
+        const cpx<T>* __restrict__ p0 = colp + static_cast<int64_t>(e0 >> 10) * nbp + bl;
+        cpx<T> v0[M];
+        if constexpr (kPair) {
+          const bool two = i + 1 < nh;
+          const int e1 = two ? lst[i + 1] : e0;
+          const cpx<T>* __restrict__ p1 = colp + static_cast<int64_t>(e1 >> 10) * nbp + bl;
+          cpx<T> v1[M];
+#pragma unroll
+          for (int k = 0; k < M; ++k) {
+            v0[k] = p0[static_cast<int64_t>(k) * nbp];
+            v1[k] = p1[static_cast<int64_t>(k) * nbp];
+          }
+          accumulate(v0, e0 & 1023, true);
+          accumulate(v1, e1 & 1023, two);
+        } else {
+#pragma unroll
+          for (int k = 0; k < M; ++k) v0[k] = p0[static_cast<int64_t>(k) * nbp];
+          accumulate(v0, e0 & 1023, true);
         }
       }
 #pragma unroll
@@ -376,14 +403,15 @@ __device__ void k2r_fwd_task(const KArgs& a, int t, cpx<T>* S) {
   const int bcl = a.bcl, bmask = (1 << bcl) - 1;
   const int b0 = chunk << bcl;
   const int ny = a.ny, n1 = a.n1, m = a.m, sx = a.sx;
-  const int nb = d.nb, ncol = d.ncol;
+  const int nb = d.nb, npcol = d.npcol;
   const int32_t* __restrict__ xinv = a.xinv + d.xinv_off;
   const int32_t* __restrict__ cy = a.col_y + d.colmeta_off;
   const int32_t* __restrict__ cxi = a.col_xi + d.colmeta_off;
+  const int32_t* __restrict__ cslot = a.col_slot + d.colmeta_off;
   const int32_t* __restrict__ sst = a.slabstart + d.slab_off;
   const int nbp = d.nchunk << bcl;
   cpx<T>* __restrict__ colp = reinterpret_cast<cpx<T>*>(a.col) + d.col_off +
-                              static_cast<int64_t>(z) * ncol * nbp + b0;
+                              static_cast<int64_t>(z) * npcol * nbp + b0;
   const cpx<T>* __restrict__ gin = reinterpret_cast<const cpx<T>*>(a.in) + d.grid_off;
   const cpx<T>* twf = reinterpret_cast<const cpx<T>*>(a.twf);
   const cpx<T>* twfl = reinterpret_cast<const cpx<T>*>(a.twf_lo);
@@ -418,7 +446,7 @@ __device__ void k2r_fwd_task(const KArgs& a, int t, cpx<T>* S) {
       const int y = cy[c];
       const cpx<T> val =
           twmul<-1>(S[(cxi[c] - x_lo) * sx + ((y % m) << bcl) + bl], twf, twfl, (y * r) % ny);
-      cpx<T>* g = colp + static_cast<int64_t>(c) * nbp + bl;
+      cpx<T>* g = colp + static_cast<int64_t>(cslot[c]) * nbp + bl;
       if (acc_lds) {
         cpx<T>* p = acc + it;
         if (n1 == 1) *g = val;
@@ -458,18 +486,58 @@ __device__ void k3r_task(const KArgs& a, int t) {
   const int bcl = a.bcl, bmask = (1 << bcl) - 1;
   const int b0 = chunk << bcl;
   const int ny = a.ny, n1 = a.n1, m = a.m;
-  const int nslab = d.nslab, ncol = d.ncol;
+  const int nslab = d.nslab, npcol = d.npcol;
   const int nbp = d.nchunk << bcl;
   const cpx<T>* __restrict__ zp = reinterpret_cast<const cpx<T>*>(a.col) + d.zp_off +
                                   static_cast<int64_t>(z) * nslab * ny * nbp + b0;
   cpx<T>* __restrict__ colp = reinterpret_cast<cpx<T>*>(a.col) + d.col_off +
-                              static_cast<int64_t>(z) * ncol * nbp + b0;
+                              static_cast<int64_t>(z) * npcol * nbp + b0;
   const int32_t* __restrict__ cidx = a.colidx + d.colidx_off;
   const cpx<T>* twf = reinterpret_cast<const cpx<T>*>(a.twf);
   const cpx<T>* twfl = reinterpret_cast<const cpx<T>*>(a.twf_lo);
   const float inv_m = 1.0f / static_cast<float>(m);
   const int items = (nslab * m) << bcl;
-  const bool codelet = codelet_radix(n1);
+  if (codelet_radix(n1)) {
+    // NP items per thread per round (two in FP32); the partials and the column
+    // slots of all of them are requested before any of them is used
+    constexpr int NP = sizeof(T) == 4 ? 2 : 1;
+    for (int it0 = threadIdx.x; it0 < items; it0 += NP * blockDim.x) {
+      cpx<T> u[NP][kMaxRadixDev];
+      int cs[NP][kMaxRadixDev];
+      bool ok[NP];
+      int bls[NP];
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        const int it = it0 + p * blockDim.x;
+        ok[p] = it < items;
+        const int iv = ok[p] ? it : it0;
+        const int bl = iv & bmask;
+        const int jx = iv >> bcl;
+        const int xi = div_small(jx, m, inv_m);
+        const int j = jx - xi * m;
+        bls[p] = bl;
+        const cpx<T>* __restrict__ src = zp + (static_cast<int64_t>(xi) * ny + j * n1) * nbp + bl;
+        const int32_t* __restrict__ crow = cidx + xi * ny + j;
+#pragma unroll
+        for (int r = 0; r < kMaxRadixDev; ++r) {
+          if (r < n1) {
+            u[p][r] = src[r * nbp];
+            cs[p][r] = crow[r * m];
+          }
+        }
+      }
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        if (!ok[p]) continue;
+        butterfly<-1>(n1, u[p]);
+#pragma unroll
+        for (int q = 0; q < kMaxRadixDev; ++q)
+          if (q < n1 && cs[p][q] >= 0) colp[static_cast<int64_t>(cs[p][q]) * nbp + bls[p]] = u[p][q];
+      }
+    }
+    return;
+  }
+  // class counts without a codelet: direct sums
   for (int it = threadIdx.x; it < items; it += blockDim.x) {
     const int bl = it & bmask;
     const int jx = it >> bcl;
@@ -477,34 +545,18 @@ __device__ void k3r_task(const KArgs& a, int t) {
     const int j = jx - xi * m;
     const cpx<T>* __restrict__ src = zp + (static_cast<int64_t>(xi) * ny + j * n1) * nbp + bl;
     const int32_t* __restrict__ crow = cidx + xi * ny + j;
-    if (codelet) {
-      cpx<T> u[kMaxRadixDev];
-#pragma unroll
-      for (int r = 0; r < kMaxRadixDev; ++r)
-        if (r < n1) u[r] = src[r * nbp];
-      butterfly<-1>(n1, u);
-#pragma unroll
-      for (int q = 0; q < kMaxRadixDev; ++q) {
-        if (q < n1) {
-          const int c = crow[q * m];
-          if (c >= 0) colp[static_cast<int64_t>(c) * nbp + bl] = u[q];
-        }
+    for (int q = 0; q < n1; ++q) {
+      const int c = crow[q * m];
+      if (c < 0) continue;
+      cpx<T> acc = src[0];
+      const int step = m * q;  // w_n1^{q} = w_ny^{m*q}
+      int idx = 0;
+      for (int r = 1; r < n1; ++r) {
+        idx += step;
+        if (idx >= ny) idx -= ny;
+        acc = cadd(acc, twmul<-1>(src[r * nbp], twf, twfl, idx));
       }
-    } else {
-      // class counts without a codelet: direct sums
-      for (int q = 0; q < n1; ++q) {
-        const int c = crow[q * m];
-        if (c < 0) continue;
-        cpx<T> acc = src[0];
-        const int step = m * q;  // w_n1^{q} = w_ny^{m*q}
-        int idx = 0;
-        for (int r = 1; r < n1; ++r) {
-          idx += step;
-          if (idx >= ny) idx -= ny;
-          acc = cadd(acc, twmul<-1>(src[r * nbp], twf, twfl, idx));
-        }
-        colp[static_cast<int64_t>(c) * nbp + bl] = acc;
-      }
+      colp[static_cast<int64_t>(c) * nbp + bl] = acc;
     }
   }
 }

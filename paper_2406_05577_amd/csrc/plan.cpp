@@ -159,29 +159,6 @@ int build_sphere_tables(int nx, int ny, int nz, const int32_t* map, int64_t ns, 
   st.colidx.assign(static_cast<size_t>(st.nslab) * ny, -1);
   for (int c = 0; c < ncol; ++c)
     st.colidx[static_cast<size_t>(st.col_xi[c]) * ny + st.col_y[c]] = c;
-  st.slab_runs.assign(static_cast<size_t>(st.nslab) * 4, 0);
-  st.two_runs = true;
-  for (int xi = 0; xi < st.nslab; ++xi) {
-    const int c0 = st.slabstart[xi], c1 = st.slabstart[xi + 1];
-    int breaks = 0, cut = c1;
-    for (int c = c0 + 1; c < c1; ++c)
-      if (st.col_y[c] != st.col_y[c - 1] + 1) {
-        ++breaks;
-        cut = c;
-      }
-    if (breaks > 1) {
-      st.two_runs = false;
-      continue;
-    }
-    int32_t* r = &st.slab_runs[static_cast<size_t>(xi) * 4];
-    r[0] = st.col_y[c0];
-    r[1] = st.col_y[cut - 1] + 1;
-    if (cut < c1) {
-      r[2] = st.col_y[cut];
-      r[3] = st.col_y[c1 - 1] + 1;
-    }
-  }
-  if (!st.two_runs) std::fill(st.slab_runs.begin(), st.slab_runs.end(), 0);
   st.slab_order.resize(st.nslab);
   for (int xi = 0; xi < st.nslab; ++xi) st.slab_order[xi] = xi;
   std::stable_sort(st.slab_order.begin(), st.slab_order.end(), [&st](int p, int q) {

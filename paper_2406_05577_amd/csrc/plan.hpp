@@ -53,11 +53,6 @@ struct SphereTables {
   std::vector<int32_t> xinv;           // nx entries: slab index or -1
   std::vector<int32_t> slabstart;      // nslab+1 entries: first column of each slab
   std::vector<int32_t> colidx;         // nslab*ny: column index or -1
-  // Each slab's sorted y values as at most two runs of consecutive values:
-  // [a0, a1) then [b0, b1) (4 entries per slab); two_runs is false if some slab
-  // needs more (then the entries are zero and unused).
-  std::vector<int32_t> slab_runs;
-  bool two_runs = true;
   std::vector<int32_t> slab_order;     // slab indices by descending column count
   std::vector<int32_t> gidx;           // ncol*nz: coefficient index or -1
   std::vector<int32_t> entry_col, entry_z;  // per coefficient
