@@ -103,6 +103,9 @@ typedef struct {
                            kernel turns into columns (a length-n1 DFT over the classes;
                            needs the register-line column kernel and one split) */
   int32_t splits;       /* forward only: column splits per (plane, chunk), 1..8 */
+  int32_t lanes;        /* register path: lanes per transform line (x lines of the plane
+                           kernel, z lines of the column kernel): 0 = choose, or 1, 4, 8, 16
+                           where a line shape of that many lanes is compiled */
 } fftb_dir_tuning;
 
 /* Tiling knobs of both directions (they are chosen and tuned independently). */

@@ -167,11 +167,11 @@ bool single_codelet(int m) {
   return false;
 }
 
-// Register shape (E values per lane, H lanes per line) for a line of length n.
-bool reg_shape(int n, bool fp64, int& E, int& H) {
-  (void)fp64;
-  const int hmax = 8;
-  for (int h = hmax; h >= 1; h >>= 1) {
+// Register shape (E values per lane, H lanes per line) for a line of length n:
+// the most lanes with a compiled shape, or exactly `lanes` if given.
+bool reg_shape(int n, bool fp64, int& E, int& H, int lanes = 0) {
+  for (int h = 16; h >= 1; h >>= 1) {
+    if (lanes && h != lanes) continue;
     if (n % h) continue;
     if (reg_shape_supported(fp64, n / h, h)) {
       E = n / h;
@@ -280,7 +280,11 @@ fftb_status choose_dir(fftb_plan_s& P, int d, const fftb_dir_tuning& t) {
   D.threads = threads;
   // ---- column kernel
   int e1 = 0, h1 = 0;
-  D.reg1 = t.path != 1 && reg_shape(P.nz, fp64, e1, h1);
+  if (t.lanes != 0 && t.lanes != 1 && t.lanes != 4 && t.lanes != 8 && t.lanes != 16)
+    return fail(FFTB_ERR_INVALID, "lanes must be 0, 1, 4, 8 or 16");
+  // the matrix-core DFT_16 runs on lines of 16 values per lane over 8 lanes
+  const int lanes = t.lanes ? t.lanes : ((P.flags & FFTB_PLAN_MFMA) && !fp64 ? 8 : 0);
+  D.reg1 = t.path != 1 && (reg_shape(P.nz, fp64, e1, h1, lanes) || reg_shape(P.nz, fp64, e1, h1));
   D.e1 = e1;
   D.h1 = h1;
   if (D.reg1) {
@@ -334,7 +338,7 @@ fftb_status choose_dir(fftb_plan_s& P, int d, const fftb_dir_tuning& t) {
   };
   D.fwd_cls = false;
   D.fold_m = 0;
-  if (t.path != 1 && reg_shape(P.nx, fp64, e2, h2)) {
+  if (t.path != 1 && (reg_shape(P.nx, fp64, e2, h2, lanes) || reg_shape(P.nx, fp64, e2, h2))) {
     if (inverse) {
       // prefer a class length with a compiled register fold
       pick_classes(true, false);
@@ -931,15 +935,17 @@ uint64_t plan_key(const int32_t dims[3], const fftb_sphere* spheres, int nsph, f
   return h;
 }
 
-constexpr int kTuneInts = 16;
+constexpr int kDirInts = static_cast<int>(sizeof(fftb_dir_tuning) / sizeof(int32_t));
+constexpr int kTuneInts = 2 * kDirInts;
+constexpr const char* kTuneTag = "fftb-tune-v2";
 
 void tuning_to_ints(const fftb_tuning& t, int32_t* v) {
-  std::memcpy(v, &t.inv, 8 * sizeof(int32_t));
-  std::memcpy(v + 8, &t.fwd, 8 * sizeof(int32_t));
+  std::memcpy(v, &t.inv, kDirInts * sizeof(int32_t));
+  std::memcpy(v + kDirInts, &t.fwd, kDirInts * sizeof(int32_t));
 }
 void ints_to_tuning(const int32_t* v, fftb_tuning& t) {
-  std::memcpy(&t.inv, v, 8 * sizeof(int32_t));
-  std::memcpy(&t.fwd, v + 8, 8 * sizeof(int32_t));
+  std::memcpy(&t.inv, v, kDirInts * sizeof(int32_t));
+  std::memcpy(&t.fwd, v + kDirInts, kDirInts * sizeof(int32_t));
 }
 
 bool cache_lookup(uint64_t key, fftb_tuning& t) {
@@ -947,15 +953,24 @@ bool cache_lookup(uint64_t key, fftb_tuning& t) {
   if (!path || !*path) return false;
   FILE* f = std::fopen(path, "r");
   if (!f) return false;
-  char tag[32];
-  unsigned long long k;
+  char line[512];
   bool found = false;
-  while (std::fscanf(f, "%31s %llx", tag, &k) == 2) {
+  while (std::fgets(line, sizeof line, f)) {
+    // "<tag> <hex key> <ints>": lines of another format version are skipped
+    char tag[32];
+    unsigned long long k;
+    int used = 0;
+    if (std::sscanf(line, "%31s %llx%n", tag, &k, &used) != 2) continue;
+    if (std::strcmp(tag, kTuneTag) != 0 || k != key) continue;
     int32_t v[kTuneInts];
+    const char* p = line + used;
     bool ok = true;
-    for (int i = 0; i < kTuneInts && ok; ++i) ok = std::fscanf(f, "%d", &v[i]) == 1;
-    if (!ok) break;
-    if (std::strcmp(tag, "fftb-tune-v1") == 0 && k == key) {
+    for (int i = 0; i < kTuneInts && ok; ++i) {
+      int n = 0;
+      ok = std::sscanf(p, "%d%n", &v[i], &n) == 1;
+      p += n;
+    }
+    if (ok) {
       ints_to_tuning(v, t);
       found = true;
     }
@@ -971,7 +986,7 @@ void cache_store(uint64_t key, const fftb_tuning& t) {
   if (!f) return;
   int32_t v[kTuneInts];
   tuning_to_ints(t, v);
-  std::fprintf(f, "fftb-tune-v1 %llx", static_cast<unsigned long long>(key));
+  std::fprintf(f, "%s %llx", kTuneTag, static_cast<unsigned long long>(key));
   for (int i = 0; i < kTuneInts; ++i) std::fprintf(f, " %d", v[i]);
   std::fprintf(f, "\n");
   std::fclose(f);
@@ -998,6 +1013,10 @@ std::vector<fftb_dir_tuning> candidates(const fftb_plan_s& P, bool inverse, cons
           t.threads = threads;
           t.path = 0;
           out.push_back(t);
+          if (bc == bc0) {
+            t.lanes = 8;  // the 8-lane line shapes against the default (most lanes)
+            out.push_back(t);
+          }
         } else {
           for (int acc : {3, 1, 2}) {
             for (int extra : {0, 1}) {
@@ -1010,6 +1029,10 @@ std::vector<fftb_dir_tuning> candidates(const fftb_plan_s& P, bool inverse, cons
               t.acc = acc;
               t.splits = extra ? -1 : 0;  // -1: one more split than the smallest that fits
               out.push_back(t);
+              if (acc == 3 && bc == bc0) {
+                t.lanes = 8;
+                out.push_back(t);
+              }
             }
           }
         }
@@ -1184,6 +1207,7 @@ fftb_status fftb_plan_create(fftb_plan* out, const int32_t dims[3], const fftb_s
       o.path = (D.reg1 && D.reg2) ? 2 : (D.reg1 || D.reg2) ? 0 : 1;
       o.acc = d == 0 ? 0 : D.fwd_cls ? 3 : (D.reg2 && D.acc_lds) ? 1 : 2;
       o.splits = D.nsplit;
+      o.lanes = D.reg2 ? D.h2 : (D.reg1 ? D.h1 : 0);
     }
     if (!(flags & FFTB_PLAN_HOST_ONLY)) {
       fftb_status st = device_setup(*P, static_cast<hipStream_t>(stream));

@@ -54,6 +54,8 @@ __device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b) {
 }
 template <typename T>
 __device__ __forceinline__ cpx<T> cscale(cpx<T> a, T s) { return {a.re * s, a.im * s}; }
+__device__ __forceinline__ float ffma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double ffma(double a, double b, double c) { return __builtin_fma(a, b, c); }
 // multiply by S*i
 template <int S, typename T>
 __device__ __forceinline__ cpx<T> mul_si(cpx<T> a) {
@@ -294,13 +296,6 @@ __device__ __forceinline__ cpx<T> twmul(cpx<T> v, const cpx<T>* __restrict__ hi,
 }
 
 // ---------------------------------------------------------------------------
-// Cross-lane exchange inside a wavefront (xor pattern), through the LDS
-// crossbar (no LDS allocation).
-template <typename T>
-__device__ __forceinline__ cpx<T> lane_xor(cpx<T> v, int mask) {
-  return {__shfl_xor(v.re, mask), __shfl_xor(v.im, mask)};
-}
-
 __device__ __forceinline__ int bitrev_bits(int h, int bits) {
   int r = 0;
   for (int i = 0; i < bits; ++i) r |= ((h >> i) & 1) << (bits - 1 - i);
@@ -314,14 +309,15 @@ constexpr int log2_const() {
   return l;
 }
 
-// exp(S*2*pi*i*j/8), j < 8 (the roots needed by the cross-lane radix-2 rounds
-// for groups of up to 8 lanes).
+// exp(S*2*pi*i*j/16), j < 16 (the roots needed by the cross-lane radix-2
+// rounds for groups of up to 16 lanes).
 template <int S, typename T>
-__device__ __forceinline__ cpx<T> root8(int j) {
-  constexpr T r = static_cast<T>(0.707106781186547524400844362104849039);
-  const T c[8] = {1, r, 0, -r, -1, -r, 0, r};
-  const T sn[8] = {0, r, 1, r, 0, -r, -1, -r};
-  return {c[j & 7], static_cast<T>(S) * sn[j & 7]};
+__device__ __forceinline__ cpx<T> root16(int j) {
+  constexpr T r = static_cast<T>(kcos(2, 16)), c1 = static_cast<T>(kcos(1, 16)),
+              s1 = static_cast<T>(ksin(1, 16));
+  const T c[16] = {1, c1, r, s1, 0, -s1, -r, -c1, -1, -c1, -r, -s1, 0, s1, r, c1};
+  const T sn[16] = {0, s1, r, c1, 1, c1, r, s1, 0, -s1, -r, -c1, -1, -c1, -r, -s1};
+  return {c[j & 15], static_cast<T>(S) * sn[j & 15]};
 }
 
 // ---------------------------------------------------------------------------
@@ -384,38 +380,132 @@ __device__ __forceinline__ void dft16_mfma(cpx<float>* v) {
   }
 }
 
+// Cross-lane partner value (lane ^ M, M = 1, 2, 4 or 8) inside rows of 16
+// lanes through DPP moves: quad permutations for 1 and 2, a half-row mirror
+// followed by a quad reversal for 4 ((i ^ 7) ^ 3 = i ^ 4), a row rotation by 8
+// for 8. Every lane of a transform line is active whenever the line is.
+template <int M>
+__device__ __forceinline__ int dpp_xor_i(int v) {
+  if constexpr (M == 1) {
+    return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true);   // quad_perm [1,0,3,2]
+  } else if constexpr (M == 2) {
+    return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true);   // quad_perm [2,3,0,1]
+  } else if constexpr (M == 4) {
+    const int m = __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, true);  // row_half_mirror
+    return __builtin_amdgcn_mov_dpp(m, 0x1B, 0xF, 0xF, true);          // quad_perm [3,2,1,0]
+  } else {
+    static_assert(M == 8, "partner distance 1, 2, 4 or 8");
+    return __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, true);  // row_ror:8
+  }
+}
+template <int M>
+__device__ __forceinline__ float dpp_xor(float x) {
+  return __int_as_float(dpp_xor_i<M>(__float_as_int(x)));
+}
+template <int M>
+__device__ __forceinline__ double dpp_xor(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = dpp_xor_i<M>(static_cast<int>(b & 0xffffffffll));
+  const int hi = dpp_xor_i<M>(static_cast<int>(b >> 32));
+  return __longlong_as_double((static_cast<long long>(hi) << 32) |
+                              (static_cast<long long>(lo) & 0xffffffffll));
+}
+
+// Per-lane constants of a transform line of length N = E*H over H lanes (lane
+// h of its group): the twiddles w_N^{h*k} (k < E; kept in registers when E is
+// small, else read per line from the root table) and, per cross-lane round of
+// partner distance hs, the sign of the lane's own value (+1 keeps v + p, -1
+// forms p - v) and the round twiddle w_{2hs}^{h mod hs} (1 for the lanes that
+// keep the sum).
+template <int E, int H, int S, typename T>
+struct LineCtx {
+  static constexpr bool kHoist = E <= 10;
+  static constexpr int kRounds = H > 1 ? log2_const<H>() : 1;
+  int h;
+  const cpx<T>* rootN;
+  const cpx<T>* rootN_lo;
+  cpx<T> tw[kHoist ? E : 1];
+  cpx<T> twl[kHoist && std::is_same<T, float>::value ? E : 1];
+  T sgn[kRounds];
+  cpx<T> rw[kRounds];
+};
+
+template <int E, int H, int S, typename T>
+__device__ __forceinline__ LineCtx<E, H, S, T> line_ctx(int h, const cpx<T>* __restrict__ rootN,
+                                                        const cpx<T>* __restrict__ rootN_lo) {
+  LineCtx<E, H, S, T> c;
+  c.h = h;
+  c.rootN = rootN;
+  c.rootN_lo = rootN_lo;
+  if constexpr (LineCtx<E, H, S, T>::kHoist && H > 1) {
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      cpx<T> w = rootN[h * k];
+      if constexpr (S > 0) w.im = -w.im;
+      c.tw[k] = w;
+      if constexpr (std::is_same<T, float>::value) {
+        cpx<T> l = rootN_lo[h * k];
+        if constexpr (S > 0) l.im = -l.im;
+        c.twl[k] = l;
+      }
+    }
+  }
+  if constexpr (H > 1) {
+    int i = 0;
+#pragma unroll
+    for (int hs = H / 2; hs >= 1; hs >>= 1, ++i) {
+      const int b = (h / hs) & 1;
+      const int hl = h % hs;
+      c.sgn[i] = b ? static_cast<T>(-1) : static_cast<T>(1);
+      // w_{2*hs}^{hl} = root16(hl * 16 / (2*hs))
+      c.rw[i] = (b && hl) ? root16<S, T>(hl * (8 / hs)) : cpx<T>{1, 0};
+    }
+  }
+  return c;
+}
+
+template <int HS, int I, int E, int H, int S, typename T>
+__device__ __forceinline__ void xlane_rounds(cpx<T>* v, const LineCtx<E, H, S, T>& c) {
+  if constexpr (HS >= 1) {
+    const T sg = c.sgn[I];
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const T pr = dpp_xor<HS>(v[k].re), pi = dpp_xor<HS>(v[k].im);
+      v[k] = {ffma(sg, v[k].re, pr), ffma(sg, v[k].im, pi)};
+    }
+    if constexpr (HS > 1) {
+      const cpx<T> w = c.rw[I];
+#pragma unroll
+      for (int k = 0; k < E; ++k) v[k] = cmul(v[k], w);
+    }
+    xlane_rounds<HS / 2, I + 1, E, H, S, T>(v, c);
+  }
+}
+
 // One transform line of length N = E*H spread over H adjacent lanes of a
 // wavefront (h = position of the lane in its group). On entry lane h holds
 // x[h + H*j] in v[j] (j < E); on exit it holds X[k + E*bitrev(h)] in v[k].
 // Cooley-Tukey with N = E*H (Section 2.1): DFT_E in registers, twiddles
-// w_N^{h*k} from the forward-sign root table of N, then DFT_H across the lanes
-// as log2(H) radix-2 rounds (partner h ^ H/2, then h ^ H/4, ...).
+// w_N^{h*k}, then DFT_H across the lanes as log2(H) radix-2 rounds (partner
+// h ^ H/2, then h ^ H/4, ...) exchanged through DPP.
 template <int E, int H, int S, typename T, bool MF = false>
-__device__ __forceinline__ void line_fft(cpx<T>* v, int h, const cpx<T>* __restrict__ rootN,
-                                         const cpx<T>* __restrict__ rootN_lo) {
+__device__ __forceinline__ void line_fft(cpx<T>* v, const LineCtx<E, H, S, T>& c) {
   if constexpr (MF && E == 16 && std::is_same<T, float>::value) dft16_mfma<S>(v);
   else dft<E, S>(v);
   if constexpr (H > 1) {
-    if (h > 0) {
+    if constexpr (LineCtx<E, H, S, T>::kHoist) {
 #pragma unroll
-      for (int k = 1; k < E; ++k) v[k] = twmul<S>(v[k], rootN, rootN_lo, h * k);
-    }
-#pragma unroll
-    for (int hs = H / 2; hs >= 1; hs >>= 1) {
-      const int b = (h / hs) & 1;
-      const int hl = h % hs;
-#pragma unroll
-      for (int k = 0; k < E; ++k) {
-        const cpx<T> p = lane_xor(v[k], hs);
-        v[k] = b ? csub(p, v[k]) : cadd(v[k], p);
+      for (int k = 1; k < E; ++k) {
+        if constexpr (std::is_same<T, float>::value)
+          v[k] = cadd(cmul(v[k], c.tw[k]), cmul(v[k], c.twl[k]));
+        else
+          v[k] = cmul(v[k], c.tw[k]);
       }
-      if (b && hl) {
-        // w_{2*hs}^{hl} = root8(hl * 8 / (2*hs))
-        const cpx<T> w = root8<S, T>(hl * (4 / hs));
+    } else if (c.h > 0) {
 #pragma unroll
-        for (int k = 0; k < E; ++k) v[k] = cmul(v[k], w);
-      }
+      for (int k = 1; k < E; ++k) v[k] = twmul<S>(v[k], c.rootN, c.rootN_lo, c.h * k);
     }
+    xlane_rounds<H / 2, 0, E, H, S, T>(v, c);
   }
 }
 

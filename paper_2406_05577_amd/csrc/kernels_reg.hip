@@ -73,10 +73,12 @@ __device__ void k1r_task(const KArgs& a, int t) {
   const int items = (nl << bcl) * H;
   // with the matrix-core codelet whole waves take part: pad to 64 lanes
   const int iters = MF ? ((items + 63) & ~63) : items;
+  // the block size is a multiple of H: a thread keeps its lane position h
+  const int h = threadIdx.x % H;
+  const auto ctx = line_ctx<E, H, S, T>(h, rootz, rootz_lo);
   for (int it = threadIdx.x; it < iters; it += blockDim.x) {
     const bool valid = !MF || it < items;
-    const int iv = valid ? it : 0;
-    const int h = iv % H;
+    const int iv = valid ? it : h;
     const int rest = iv / H;
     const int bl = rest & bmask;
     const int c = c0 + (rest >> bcl);
@@ -96,7 +98,7 @@ __device__ void k1r_task(const KArgs& a, int t) {
         v[j] = valid ? colbuf[(static_cast<int64_t>(h + H * j) * npcol + slot) * nbp + bl]
                      : cpx<T>{0, 0};
     }
-    line_fft<E, H, S, T, MF>(v, h, rootz, rootz_lo);
+    line_fft<E, H, S, T, MF>(v, ctx);
     const int q = bitrev_bits(h, L);
     if (!valid) continue;
     if constexpr (S > 0) {
@@ -274,6 +276,7 @@ __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S) {
   cpx<T>* __restrict__ gout = reinterpret_cast<cpx<T>*>(a.out) + d.grid_off;
   const int h = threadIdx.x % H;
   const int q = bitrev_bits(h, L);
+  const auto ctx = line_ctx<E, H, +1, T>(h, rootx, rootx_lo);
   int xs[E];
 #pragma unroll
   for (int j = 0; j < E; ++j) xs[j] = xinv[h + H * j];
@@ -289,7 +292,7 @@ __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S) {
 #pragma unroll
     for (int j = 0; j < E; ++j)
       v[j] = (valid && xs[j] >= 0) ? S[xs[j] * sx + (k2 << bcl) + bl] : cpx<T>{0, 0};
-    line_fft<E, H, +1, T, MF>(v, h, rootx, rootx_lo);
+    line_fft<E, H, +1, T, MF>(v, ctx);
     const int y = r + n1 * k2;
     const int b = b0 + bl;
     if (valid && b < nb) {
@@ -316,6 +319,7 @@ __device__ __forceinline__ void fwd_x_rows(const KArgs& a, const cpx<T>* __restr
   const cpx<T>* rootx_lo = reinterpret_cast<const cpx<T>*>(a.rootx_lo);
   const int h = threadIdx.x % H;
   const int q = bitrev_bits(h, L);
+  const auto ctx = line_ctx<E, H, -1, T>(h, rootx, rootx_lo);
   int xs[E];
 #pragma unroll
   for (int k = 0; k < E; ++k) {
@@ -338,7 +342,7 @@ __device__ __forceinline__ void fwd_x_rows(const KArgs& a, const cpx<T>* __restr
 #pragma unroll
     for (int j = 0; j < E; ++j)
       v[j] = ld ? row[static_cast<int64_t>(h + H * j) * nb] : cpx<T>{0, 0};
-    line_fft<E, H, -1, T, MF>(v, h, rootx, rootx_lo);
+    line_fft<E, H, -1, T, MF>(v, ctx);
     if (!valid) continue;
 #pragma unroll
     for (int k = 0; k < E; ++k)
@@ -639,10 +643,12 @@ __global__ void __launch_bounds__(512) k2r_kernel(const KArgs a) {
 // (E, H) pairs compiled for each precision; the host picks one per axis.
 #define FFTB_REG_SHAPES_F64(X) \
   X(4, 1) X(5, 1) X(6, 1) X(8, 1) X(9, 1) X(10, 1) X(12, 1) X(15, 1) X(16, 1) \
-  X(5, 4) X(6, 4) X(4, 8) X(12, 8) X(16, 8) X(18, 8) X(20, 8) X(45, 4)
+  X(5, 4) X(6, 4) X(4, 8) X(12, 8) X(16, 8) X(18, 8) X(20, 8) X(45, 4)       \
+  X(6, 16) X(8, 16) X(9, 16) X(10, 16)
 #define FFTB_REG_SHAPES_F32(X) \
   X(4, 1) X(5, 1) X(6, 1) X(8, 1) X(9, 1) X(10, 1) X(12, 1) X(15, 1) X(16, 1) \
-  X(5, 4) X(6, 4) X(4, 8) X(12, 8) X(16, 8) X(18, 8) X(20, 8) X(45, 4)
+  X(5, 4) X(6, 4) X(4, 8) X(12, 8) X(16, 8) X(18, 8) X(20, 8) X(45, 4)       \
+  X(6, 16) X(8, 16) X(9, 16) X(10, 16)
 
 bool reg_shape_supported(bool fp64, int E, int H) {
 #define FFTB_CHK(e, h) if (E == e && H == h) return true;
@@ -656,8 +662,8 @@ bool reg_shape_supported(bool fp64, int E, int H) {
 }
 
 // Inverse plane kernels with a compile-time class length are compiled for the
-// lines spread over 8 lanes (x lengths 32 .. 160) and m = 8 or 16.
-constexpr bool fold_m_compiled(int H, int m) { return H == 8 && (m == 8 || m == 16); }
+// lines spread over 8 or 16 lanes (x lengths 32 .. 160) and m = 8 or 16.
+constexpr bool fold_m_compiled(int H, int m) { return (H == 8 || H == 16) && (m == 8 || m == 16); }
 
 template <int S, typename T, int E, int H, bool MF, bool FC, int M>
 static hipError_t launch_k2(const KArgs& a, int grid, int threads, size_t lds, hipStream_t st) {

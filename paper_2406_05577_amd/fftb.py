@@ -45,7 +45,8 @@ class Sphere_t(C.Structure):
                 ("kpt", C.c_double * 3), ("nbands", C.c_int32)]
 
 
-DIR_FIELDS = ["band_chunk", "y_classes", "x_rows", "col_tile", "threads", "path", "acc", "splits"]
+DIR_FIELDS = ["band_chunk", "y_classes", "x_rows", "col_tile", "threads", "path", "acc", "splits",
+              "lanes"]
 
 
 class DirTuning_t(C.Structure):

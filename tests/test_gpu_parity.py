@@ -186,7 +186,7 @@ def test_autotune_and_cache(tmp_path, monkeypatch):
         p2.close()
         e = check_workload(w, dtype, flags=2)
         assert max(e) <= TOL[dtype], e
-    assert (tmp_path / "tune.txt").read_text().count("fftb-tune-v1") == 2
+    assert (tmp_path / "tune.txt").read_text().count("fftb-tune-v2") == 2
 
 
 @pytest.mark.parametrize("flags", [16, 16 | 1 | 4])
