@@ -167,7 +167,8 @@ def main():
     ap.add_argument("--tuning", default=None, help="JSON dict of tiling knobs")
     ap.add_argument("--autotune", action="store_true",
                     help="let the library time candidate tilings at plan creation (not timed)")
-    ap.add_argument("--cpu-sample-bands", type=int, default=48)
+    ap.add_argument("--cpu-sample-bands", type=int, default=256,
+                    help="bands of the first sphere the oracle transforms (capped at the workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="skip per-kernel event timing (graph replays never record it)")

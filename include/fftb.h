@@ -101,7 +101,7 @@ typedef struct {
                            columns split over workgroups), 2 = accumulators in global memory,
                            3 = one task per y class writing class partials that a combine
                            kernel turns into columns (a length-n1 DFT over the classes;
-                           needs the register-line column kernel and one split) */
+                           one split) */
   int32_t splits;       /* forward only: column splits per (plane, chunk), 1..8 */
   int32_t lanes;        /* register path: lanes per transform line (x lines of the plane
                            kernel, z lines of the column kernel): 0 = choose, or 1, 4, 8, 16

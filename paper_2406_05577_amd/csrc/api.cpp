@@ -312,8 +312,10 @@ fftb_status choose_dir(fftb_plan_s& P, int d, const fftb_dir_tuning& t) {
   // two workgroups per CU unless the class count is fixed)
   // want_fold_m: only class lengths with a compiled inverse fold; want_codelet:
   // only class counts with a DFT codelet (the forward combine)
+  // (inverse: the fewest classes that fit, since every class re-reads the
+  // plane's columns; forward: fit two workgroups per CU where possible)
   auto pick_classes = [&](bool want_fold_m, bool want_codelet) {
-    for (size_t cap : {n1 ? kLdsMax : kLdsMax / 2, kLdsMax}) {
+    for (size_t cap : {(n1 || inverse) ? kLdsMax : kLdsMax / 2, kLdsMax}) {
       for (int c = 1; c <= P.ny; ++c) {
         if (P.ny % c || (n1 && c != n1)) continue;
         const int m = P.ny / c;
@@ -349,7 +351,7 @@ fftb_status choose_dir(fftb_plan_s& P, int d, const fftb_dir_tuning& t) {
         // the generic fold needs no staged tables
         pick_classes(false, false);
       }
-    } else if ((t.acc == 0 || t.acc == 3) && t.splits <= 1 && D.reg1) {
+    } else if ((t.acc == 0 || t.acc == 3) && t.splits <= 1) {
       // class partials combined by a separate kernel: no accumulators
       pick_classes(false, true);
       if (!D.reg2) pick_classes(false, false);
@@ -357,7 +359,7 @@ fftb_status choose_dir(fftb_plan_s& P, int d, const fftb_dir_tuning& t) {
       if (!D.reg2 && t.acc == 3)
         return fail(FFTB_ERR_UNSUPPORTED, "no class slab fits in LDS");
     } else if (t.acc == 3) {
-      return fail(FFTB_ERR_UNSUPPORTED, "class partials need the register column kernel and no splits");
+      return fail(FFTB_ERR_UNSUPPORTED, "class partials take one column split");
     }
     if (!inverse && !D.reg2) {
       // forward: the plane's columns are split into nsplit slab ranges whose

@@ -56,6 +56,32 @@ template <typename T>
 __device__ __forceinline__ cpx<T> cscale(cpx<T> a, T s) { return {a.re * s, a.im * s}; }
 __device__ __forceinline__ float ffma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double ffma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+// u + v*w with fused multiply-adds
+template <typename T>
+__device__ __forceinline__ cpx<T> cmac(cpx<T> u, cpx<T> v, cpx<T> w) {
+  T re = ffma(v.re, w.re, u.re);
+  re = ffma(-v.im, w.im, re);
+  T im = ffma(v.re, w.im, u.im);
+  im = ffma(v.im, w.re, im);
+  return {re, im};
+}
+// v*(hi + lo) for a compensated FP32 twiddle, the small products first
+__device__ __forceinline__ cpx<float> cmul_hl(cpx<float> v, cpx<float> hi, cpx<float> lo) {
+  float re = v.re * lo.re;
+  re = ffma(-v.im, lo.im, re);
+  re = ffma(v.re, hi.re, re);
+  re = ffma(-v.im, hi.im, re);
+  float im = v.re * lo.im;
+  im = ffma(v.im, lo.re, im);
+  im = ffma(v.re, hi.im, im);
+  im = ffma(v.im, hi.re, im);
+  return {re, im};
+}
+// u + v*(hi + lo)
+__device__ __forceinline__ cpx<float> cmac_hl(cpx<float> u, cpx<float> v, cpx<float> hi,
+                                              cpx<float> lo) {
+  return cmac(cmac(u, v, lo), v, hi);
+}
 // multiply by S*i
 template <int S, typename T>
 __device__ __forceinline__ cpx<T> mul_si(cpx<T> a) {
@@ -287,8 +313,7 @@ __device__ __forceinline__ cpx<T> twmul(cpx<T> v, const cpx<T>* __restrict__ hi,
   if constexpr (std::is_same<T, float>::value) {
     cpx<T> l = lo[idx];
     if constexpr (S > 0) l.im = -l.im;
-    const cpx<T> a = cmul(v, w), b = cmul(v, l);
-    return cadd(a, b);
+    return cmul_hl(v, w, l);
   } else {
     (void)lo;
     return cmul(v, w);
@@ -497,7 +522,7 @@ __device__ __forceinline__ void line_fft(cpx<T>* v, const LineCtx<E, H, S, T>& c
 #pragma unroll
       for (int k = 1; k < E; ++k) {
         if constexpr (std::is_same<T, float>::value)
-          v[k] = cadd(cmul(v[k], c.tw[k]), cmul(v[k], c.twl[k]));
+          v[k] = cmul_hl(v[k], c.tw[k], c.twl[k]);
         else
           v[k] = cmul(v[k], c.tw[k]);
       }

@@ -76,42 +76,65 @@ __device__ void k1r_task(const KArgs& a, int t) {
   // the block size is a multiple of H: a thread keeps its lane position h
   const int h = threadIdx.x % H;
   const auto ctx = line_ctx<E, H, S, T>(h, rootz, rootz_lo);
-  for (int it = threadIdx.x; it < iters; it += blockDim.x) {
-    const bool valid = !MF || it < items;
-    const int iv = valid ? it : h;
-    const int rest = iv / H;
-    const int bl = rest & bmask;
-    const int c = c0 + (rest >> bcl);
-    const int slot = cslot[c];
-    const int b = b0 + bl;
-    cpx<T> v[E];
+  // NP lines per thread per round (two for short lines): the table lookups and
+  // loads of all of them are issued before any is used
+  constexpr int NP = (E <= 10 && !MF) ? 2 : 1;
+  const int q = bitrev_bits(h, L);
+  for (int it0 = threadIdx.x; it0 < iters; it0 += NP * blockDim.x) {
+    bool ok[NP];
+    int cc[NP], slot[NP], bls[NP];
+    cpx<T> v[NP][E];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      const int it = it0 + p * blockDim.x;
+      // with the matrix-core codelet padded lanes still run the transform
+      ok[p] = MF ? it < items : it < iters;
+      const int iv = ok[p] ? it : h;
+      const int rest = iv / H;
+      bls[p] = rest & bmask;
+      cc[p] = c0 + (rest >> bcl);
+      slot[p] = cslot[cc[p]];
+    }
     if constexpr (S > 0) {
       const cpx<T>* __restrict__ in = reinterpret_cast<const cpx<T>*>(a.in) + d.sph_off;
+      int g[NP][E];
 #pragma unroll
-      for (int j = 0; j < E; ++j) {
-        const int g = gidx[c * nz + h + H * j];
-        v[j] = (valid && g >= 0 && b < nb) ? in[static_cast<int64_t>(g) * nb + b] : cpx<T>{0, 0};
+      for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int j = 0; j < E; ++j) g[p][j] = gidx[cc[p] * nz + h + H * j];
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        const int b = b0 + bls[p];
+#pragma unroll
+        for (int j = 0; j < E; ++j)
+          v[p][j] = (ok[p] && g[p][j] >= 0 && b < nb) ? in[static_cast<int64_t>(g[p][j]) * nb + b]
+                                                       : cpx<T>{0, 0};
       }
     } else {
 #pragma unroll
-      for (int j = 0; j < E; ++j)
-        v[j] = valid ? colbuf[(static_cast<int64_t>(h + H * j) * npcol + slot) * nbp + bl]
-                     : cpx<T>{0, 0};
+      for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int j = 0; j < E; ++j)
+          v[p][j] = ok[p] ? colbuf[(static_cast<int64_t>(h + H * j) * npcol + slot[p]) * nbp + bls[p]]
+                          : cpx<T>{0, 0};
     }
-    line_fft<E, H, S, T, MF>(v, ctx);
-    const int q = bitrev_bits(h, L);
-    if (!valid) continue;
-    if constexpr (S > 0) {
 #pragma unroll
-      for (int k = 0; k < E; ++k)
-        colbuf[(static_cast<int64_t>(k + E * q) * npcol + slot) * nbp + bl] = v[k];
-    } else {
-      cpx<T>* __restrict__ out = reinterpret_cast<cpx<T>*>(a.out) + d.sph_off;
-      const T sc = static_cast<T>(a.scale);
+    for (int p = 0; p < NP; ++p) {
+      line_fft<E, H, S, T, MF>(v[p], ctx);
+      if (!ok[p]) continue;
+      if constexpr (S > 0) {
 #pragma unroll
-      for (int k = 0; k < E; ++k) {
-        const int g = gidx[c * nz + k + E * q];
-        if (g >= 0 && b < nb) out[static_cast<int64_t>(g) * nb + b] = cscale(v[k], sc);
+        for (int k = 0; k < E; ++k)
+          colbuf[(static_cast<int64_t>(k + E * q) * npcol + slot[p]) * nbp + bls[p]] = v[p][k];
+      } else {
+        cpx<T>* __restrict__ out = reinterpret_cast<cpx<T>*>(a.out) + d.sph_off;
+        const T sc = static_cast<T>(a.scale);
+        const int b = b0 + bls[p];
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+          const int g = gidx[cc[p] * nz + k + E * q];
+          if (g >= 0 && b < nb) out[static_cast<int64_t>(g) * nb + b] = cscale(v[p][k], sc);
+        }
       }
     }
   }
@@ -191,10 +214,10 @@ __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S) {
           cpx<T> wl = troot[2 * tb + 1];
           if (!use) wl = cpx<T>{0, 0};
 #pragma unroll
-          for (int k = 0; k < M; ++k) u[k] = cadd(u[k], cadd(cmul(v[k], w), cmul(v[k], wl)));
+          for (int k = 0; k < M; ++k) u[k] = cmac_hl(u[k], v[k], w, wl);
         } else {
 #pragma unroll
-          for (int k = 0; k < M; ++k) u[k] = cadd(u[k], cmul(v[k], w));
+          for (int k = 0; k < M; ++k) u[k] = cmac(u[k], v[k], w);
         }
       };
       for (int i = 0; i < nh; i += (kPair ? 2 : 1)) {
