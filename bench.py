@@ -34,6 +34,10 @@ WORKLOADS = {
     "c4_fp64": ("c4", "c128", 0),
     "c5": ("c5", "c64", 1 | 4),
     "c5_fp64": ("c5", "c128", 0),
+    # padded-cube comparator: the same bands scattered into the whole grid and
+    # transformed without pruning (every column, every slab)
+    "c2_full": ("c2", "c128", 0),
+    "c3_full": ("c3", "c64", 0),
 }
 DESCR = {
     "c1": "sphere<->grid 32^3, |G|<=8 (2109 coeffs), Gamma, 4 bands",
@@ -42,6 +46,9 @@ DESCR = {
     "c3alt": "sphere<->grid 32^3, |G|<=8 (2109 coeffs), Gamma, 256 bands",
     "c4": "sphere<->grid 96^3, 8 k-points, |G+k|<=24, 64 bands each (512 spheres)",
     "c5": "sphere<->grid 144x160x180, ellipsoid (36,40,45), 4 k-points, 128 bands each",
+    "c2_full": "padded-cube comparator: the 128^3, |G|<=32, 256-band sphere scattered into the "
+               "full grid, transformed with every column and slab (no pruning)",
+    "c3_full": "padded-cube comparator of c3 (complex64)",
 }
 
 
@@ -199,20 +206,38 @@ def main():
     tuning = json.loads(args.tuning) if args.tuning else None
     torch.cuda.set_device(0)
     w = synth.make_workload(recipe, dtype=dtype)
-    t_plan = time.perf_counter()
-    plan = Plan(w.dims, [s.lin for s in w.spheres], [s.nbands for s in w.spheres],
-                kpts=[s.kpt for s in w.spheres], dtype=dtype, flags=flags, tuning=tuning)
-    t_plan = time.perf_counter() - t_plan
+    full = args.workload.endswith("_full")
     tdt = torch.complex128 if dtype == "c128" else torch.complex64
-    sph = torch.from_numpy(w.sphere_concat()).to("cuda").to(tdt)
+    t_plan = time.perf_counter()
+    if full:
+        # one "sphere" holding every grid point; the coefficients of the
+        # (single) sphere are scattered into it on the device
+        assert len(w.spheres) == 1
+        s0 = w.spheres[0]
+        all_pts = np.arange(w.ngrid, dtype=np.int32)
+        plan = Plan(w.dims, [all_pts], [s0.nbands], kpts=[s0.kpt], dtype=dtype, flags=flags,
+                    tuning=tuning)
+    else:
+        plan = Plan(w.dims, [s.lin for s in w.spheres], [s.nbands for s in w.spheres],
+                    kpts=[s.kpt for s in w.spheres], dtype=dtype, flags=flags, tuning=tuning)
+    t_plan = time.perf_counter() - t_plan
+    if full:
+        sph = torch.zeros((w.ngrid, w.spheres[0].nbands), dtype=tdt, device="cuda")
+        sph[torch.from_numpy(w.spheres[0].lin.astype(np.int64)).to("cuda")] = \
+            torch.from_numpy(w.coeffs[0]).to("cuda").to(tdt)
+        sph = sph.reshape(-1)
+    else:
+        sph = torch.from_numpy(w.sphere_concat()).to("cuda").to(tdt)
     back = torch.empty_like(sph)
     grid = torch.empty(plan.info["grid_elems"], dtype=tdt, device="cuda")
     es = 16 if dtype == "c128" else 8
     N = w.ngrid
     nb_total = w.nbands_total
-    sphere_bytes = plan.info["sphere_elems"] * es
     grid_bytes = plan.info["grid_elems"] * es
-    b_min = 2 * (grid_bytes + sphere_bytes)       # algorithmic bytes per round trip
+    # algorithmic bytes per round trip of the pruned problem (for the padded
+    # cube too, so that the two figures compare)
+    sphere_bytes = sum(s.ns * s.nbands for s in w.spheres) * es
+    b_min = 2 * (grid_bytes + sphere_bytes)
 
     def step():
         plan.sphere_to_grid(sph, grid)
@@ -278,7 +303,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if dtype == "c128" else "f32",
         "data": "synthetic (seeded complex Gaussian bands on the cutoff sphere)",
-        "config": {"workload": DESCR.get(recipe, recipe), "recipe": recipe,
+        "config": {"workload": DESCR.get(args.workload, DESCR.get(recipe, recipe)), "recipe": recipe,
                    "complex_dtype": "complex128" if dtype == "c128" else "complex64",
                    "dims": list(w.dims), "bands": nb_total, "spheres": len(w.spheres),
                    "coeffs": int(plan.info["total_coeffs"]), "plan_flags": flags,

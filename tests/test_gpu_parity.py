@@ -154,6 +154,24 @@ def test_directions_keep_their_scratch(dtype):
     assert torch.isfinite(g2).all()
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_full_cube_map(dtype):
+    """A map holding every grid point (the padded-cube comparator: no pruning
+    left, every column and slab occupied) against the oracle."""
+    dims = (16, 12, 10)
+    lin = np.arange(dims[0] * dims[1] * dims[2], dtype=np.int32)
+    lin = lin[np.random.default_rng(3).permutation(lin.shape[0])]
+    nx, ny = dims[0], dims[1]
+    m = np.stack([lin % nx, (lin // nx) % ny, lin // (nx * ny)], axis=1).astype(np.int64)
+    nb = 6
+    c = synth.draw_coefficients(np.random.default_rng(4), lin.shape[0], nb)
+    dt = np.complex128 if dtype == "c128" else np.complex64
+    w = synth.Workload(name="cube", dims=dims, spheres=[synth.Sphere(m=m, lin=lin, kpt=(0, 0, 0), nbands=nb)],
+                       coeffs=[c.astype(dt)], dtype=np.dtype(dt), seed=4)
+    e = check_workload(w, dtype)
+    assert max(e) <= TOL[dtype], e
+
+
 def test_c1_full():
     w = synth.make_workload("c1")
     e = check_workload(w, "c128")
