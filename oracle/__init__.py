@@ -17,4 +17,5 @@ from .pwfft import (  # noqa: F401
     grid_to_sphere,
     brute_sphere_to_grid,
     brute_grid_to_sphere,
+    apply_potential,
 )

@@ -89,6 +89,20 @@ def grid_to_sphere(dims, lin, grid, order: str = "xyz") -> np.ndarray:
     return gather_sphere(lin, a) / float(nx * ny * nz)
 
 
+def apply_potential(dims, lin, coeffs, potential) -> np.ndarray:
+    """The real-space step the transforms exist for (Section 1: the Kohn-Sham
+    wavefunctions, and operations that are cheaper in real space): go to the
+    grid, multiply every band pointwise by a real local potential V(x,y,z)
+    (shape (nz, ny, nx), shared by all bands), come back to the sphere:
+    c' = grid_to_sphere(V * sphere_to_grid(c))."""
+    v = np.asarray(potential, dtype=np.float64)
+    nx, ny, nz = (int(d) for d in dims)
+    if v.shape != (nz, ny, nx):
+        raise ValueError("potential must have shape (nz, ny, nx)")
+    g = sphere_to_grid(dims, lin, coeffs)
+    return grid_to_sphere(dims, lin, g * v[..., None])
+
+
 def _phase_table(dims, m: np.ndarray, sign: int) -> np.ndarray:
     """E[g, r] = exp(sign*2*pi*j*(mx*x/nx + my*y/ny + mz*z/nz)) for every grid
     point r (x fastest), evaluated directly from the triple of fractions."""

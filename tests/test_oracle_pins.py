@@ -279,6 +279,49 @@ def _run_pins(s2g, g2s):
     return True
 
 
+# --- real-space potential step (Section 1) ----------------------------------
+
+@pytest.mark.parametrize("i", range(len(TINY)))
+def test_potential_constant_scales(i):
+    """V = v0 everywhere multiplies every coefficient by v0 (closed form)."""
+    dims, s, c = _case(i)
+    nx, ny, nz = dims
+    got = oracle.apply_potential(dims, s.lin, c, np.full((nz, ny, nx), 2.5))
+    np.testing.assert_allclose(got, 2.5 * c, atol=1e-13 * np.abs(c).max())
+
+
+@pytest.mark.parametrize("i", range(len(TINY)))
+def test_potential_cosine_couples_neighbours(i):
+    """V(x) = cos(2 pi x / nx) = (e^{+} + e^{-})/2 couples G to G -+ e_x
+    (convolution theorem): c'(G) = (c(G - e_x) + c(G + e_x)) / 2, with
+    coefficients outside the sphere counted as zero."""
+    dims, s, c = _case(i)
+    nx, ny, nz = dims
+    x = np.arange(nx)
+    v = np.broadcast_to(np.cos(2 * np.pi * x / nx), (nz, ny, nx))
+    got = oracle.apply_potential(dims, s.lin, c, v)
+    index = {tuple(int(q) for q in mm): g for g, mm in enumerate(s.m)}
+    exp = np.zeros_like(c)
+    for g, (mx, my, mz) in enumerate(s.m):
+        for d in (-1, 1):
+            h = index.get((int(mx) + d, int(my), int(mz)))
+            if h is not None:
+                exp[g] += 0.5 * c[h]
+    np.testing.assert_allclose(got, exp, atol=1e-13 * np.abs(c).max())
+
+
+@pytest.mark.parametrize("i", range(len(TINY)))
+def test_potential_brute_force(i):
+    """A random real V against the brute-force triple sums on both sides."""
+    dims, s, c = _case(i)
+    nx, ny, nz = dims
+    v = np.random.default_rng(30 + i).standard_normal((nz, ny, nx))
+    got = oracle.apply_potential(dims, s.lin, c, v)
+    g = oracle.brute_sphere_to_grid(dims, s.m, c) * v[..., None]
+    ref = oracle.brute_grid_to_sphere(dims, s.m, g)
+    assert rel(got, ref) < 1e-13
+
+
 def test_pins_pass_on_oracle():
     assert _run_pins(oracle.sphere_to_grid, oracle.grid_to_sphere)
 
