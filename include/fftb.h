@@ -153,6 +153,16 @@ fftb_status fftb_plan_create(fftb_plan* out, const int32_t dims[3],
                              fftb_dtype dtype, uint32_t flags,
                              const fftb_tuning* tuning, void* stream);
 
+/* The classic batched cuboid transform (the paper's first API example,
+ * Section 3.2, a 3D FFT of a batch of cuboid grids): a plan whose single
+ * "sphere" is every grid point in G[z][y][x] order, so that both buffers hold
+ * N * nbands values in the grid layout. sphere_to_grid is then the
+ * unnormalised inverse 3D DFT of the batch and grid_to_sphere the forward one
+ * scaled by 1/N. Arguments and errors as for fftb_plan_create (nbands >= 1). */
+fftb_status fftb_plan_create_cuboid(fftb_plan* out, const int32_t dims[3], int32_t nbands,
+                                    fftb_dtype dtype, uint32_t flags,
+                                    const fftb_tuning* tuning, void* stream);
+
 /* Inverse transform (sphere -> grid) of every band of every sphere.
  * sphere_in: device pointer, info.sphere_elems complex values (read only).
  * grid_out:  device pointer, info.grid_elems complex values (fully written).
@@ -165,6 +175,18 @@ fftb_status fftb_sphere_to_grid(fftb_plan plan, const void* sphere_in, void* gri
  * sphere_out: device pointer, info.sphere_elems complex values (fully written). */
 fftb_status fftb_grid_to_sphere(fftb_plan plan, const void* grid_in, void* sphere_out,
                                 void* stream);
+
+/* Real-space step between the two transforms (Section 1 of the paper: the
+ * Kohn-Sham wavefunctions, and operations that are cheaper in real space):
+ * for every band, psi = sphere_to_grid(c); psi(x,y,z) *= V(x,y,z);
+ * c' = grid_to_sphere(psi). The multiply is fused into the stores of the
+ * inverse plane kernel, so the step moves the bytes of one round trip.
+ * potential:  device pointer, N real values (double for FFTB_C128, float for
+ *             FFTB_C64) in V[z][y][x] order, shared by all bands and spheres.
+ * grid_work:  device pointer, info.grid_elems complex values; receives V*psi.
+ * sphere_in / sphere_out: as for the two transforms (must not overlap grid_work). */
+fftb_status fftb_apply_potential(fftb_plan plan, const void* sphere_in, const void* potential,
+                                 void* grid_work, void* sphere_out, void* stream);
 
 /* Fill *info. Valid for host-only plans too. */
 fftb_status fftb_plan_get_info(fftb_plan plan, fftb_plan_info* info);

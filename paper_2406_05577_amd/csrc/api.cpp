@@ -119,6 +119,7 @@ struct fftb_plan_s {
     hipGraph_t graph = nullptr;
     const void* in = nullptr;
     void* out = nullptr;
+    const void* pot = nullptr;
   } gc[2];
   hipStream_t cap_stream = nullptr;
   // per-kernel timing
@@ -352,8 +353,19 @@ fftb_status choose_dir(fftb_plan_s& P, int d, const fftb_dir_tuning& t) {
         pick_classes(false, false);
       }
     } else if ((t.acc == 0 || t.acc == 3) && t.splits <= 1) {
-      // class partials combined by a separate kernel: no accumulators
+      // class partials combined by a separate kernel: no accumulators; a class
+      // count with a DFT codelet for the combine, halving the band chunk once
+      // if none fits
       pick_classes(false, true);
+      if (!D.reg2 && !t.band_chunk && bc > 1) {
+        bc /= 2;
+        D.bc = bc;
+        pick_classes(false, true);
+        if (!D.reg2) {
+          bc *= 2;
+          D.bc = bc;
+        }
+      }
       if (!D.reg2) pick_classes(false, false);
       D.fwd_cls = D.reg2;
       if (!D.reg2 && t.acc == 3)
@@ -724,7 +736,8 @@ fftb_status device_setup(fftb_plan_s& P, hipStream_t st) {
   return FFTB_OK;
 }
 
-KArgs make_args(const fftb_plan_s& P, const DirCfg& D, const void* in, void* out, bool inverse) {
+KArgs make_args(const fftb_plan_s& P, const DirCfg& D, const void* in, void* out, bool inverse,
+                const void* pot) {
   KArgs a;
   std::memset(&a, 0, sizeof a);
   a.nx = P.nx;
@@ -779,6 +792,7 @@ KArgs make_args(const fftb_plan_s& P, const DirCfg& D, const void* in, void* out
   a.rootz_lo = P.d_rootz_lo;
   a.in = in;
   a.out = out;
+  a.pot = inverse ? pot : nullptr;
   a.col = P.d_col;
   a.scale = inverse ? 1.0 : 1.0 / (static_cast<double>(P.nx) * P.ny * P.nz);
   a.counters = P.d_counters;
@@ -869,7 +883,8 @@ hipError_t enqueue(fftb_plan_s* P, const KArgs& a, const DirCfg& D, bool inverse
   return hipSuccess;
 }
 
-fftb_status run(fftb_plan_s* P, const void* in, void* out, void* stream, bool inverse) {
+fftb_status run(fftb_plan_s* P, const void* in, void* out, void* stream, bool inverse,
+                const void* pot = nullptr) {
   if (!P) return fail(FFTB_ERR_INVALID, "null plan");
   if (!P->device) return fail(FFTB_ERR_INVALID, "plan was created host-only");
   if (!in || !out) return fail(FFTB_ERR_INVALID, "null data pointer");
@@ -877,10 +892,10 @@ fftb_status run(fftb_plan_s* P, const void* in, void* out, void* stream, bool in
   const DirCfg& D = P->dir[inverse ? 0 : 1];
   int g1, g2, g3;
   grids(*P, D, g1, g2, g3);
-  KArgs a = make_args(*P, D, in, out, inverse);
+  KArgs a = make_args(*P, D, in, out, inverse, pot);
   if (P->flags & FFTB_PLAN_GRAPH) {
     auto& gc = P->gc[inverse ? 0 : 1];
-    if (!gc.exec || gc.in != in || gc.out != out) {
+    if (!gc.exec || gc.in != in || gc.out != out || gc.pot != a.pot) {
       if (gc.exec) { (void)hipGraphExecDestroy(gc.exec); gc.exec = nullptr; }
       if (gc.graph) { (void)hipGraphDestroy(gc.graph); gc.graph = nullptr; }
       if (!P->cap_stream) {
@@ -897,6 +912,7 @@ fftb_status run(fftb_plan_s* P, const void* in, void* out, void* stream, bool in
       if (e != hipSuccess) return fail(FFTB_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
       gc.in = in;
       gc.out = out;
+      gc.pot = a.pot;
     }
     hipError_t e = hipGraphLaunch(gc.exec, st);
     if (e != hipSuccess) return fail(FFTB_ERR_HIP, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
@@ -1235,6 +1251,45 @@ fftb_status fftb_sphere_to_grid(fftb_plan plan, const void* sphere_in, void* gri
 fftb_status fftb_grid_to_sphere(fftb_plan plan, const void* grid_in, void* sphere_out, void* stream) {
   try {
     return run(plan, grid_in, sphere_out, stream, false);
+  } catch (...) {
+    return fail(FFTB_ERR_INVALID, "unexpected exception");
+  }
+}
+
+fftb_status fftb_plan_create_cuboid(fftb_plan* out, const int32_t dims[3], int32_t nbands,
+                                    fftb_dtype dtype, uint32_t flags, const fftb_tuning* tuning,
+                                    void* stream) {
+  try {
+    if (!out) return fail(FFTB_ERR_INVALID, "null output pointer");
+    *out = nullptr;
+    if (!dims) return fail(FFTB_ERR_INVALID, "null dims");
+    for (int i = 0; i < 3; ++i)
+      if (dims[i] < 1) return fail(FFTB_ERR_INVALID, "dims must be >= 1");
+    const int64_t N = static_cast<int64_t>(dims[0]) * dims[1] * dims[2];
+    if (N > (int64_t{1} << 31) - 1) return fail(FFTB_ERR_UNSUPPORTED, "grid larger than 2^31 points");
+    // every grid point is a coefficient, in grid order
+    std::vector<int32_t> map(static_cast<size_t>(N));
+    for (int64_t i = 0; i < N; ++i) map[static_cast<size_t>(i)] = static_cast<int32_t>(i);
+    fftb_sphere s = {};
+    s.n_coeffs = N;
+    s.map = map.data();
+    s.nbands = nbands;
+    return fftb_plan_create(out, dims, &s, 1, dtype, flags, tuning, stream);
+  } catch (const std::bad_alloc&) {
+    return fail(FFTB_ERR_NOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(FFTB_ERR_INVALID, "unexpected exception");
+  }
+}
+
+fftb_status fftb_apply_potential(fftb_plan P, const void* sphere_in, const void* potential,
+                                 void* grid_work, void* sphere_out, void* stream) {
+  try {
+    if (!P) return fail(FFTB_ERR_INVALID, "null plan");
+    if (!potential) return fail(FFTB_ERR_INVALID, "null potential");
+    fftb_status s = run(P, sphere_in, grid_work, stream, true, potential);
+    if (s != FFTB_OK) return s;
+    return run(P, grid_work, sphere_out, stream, false);
   } catch (...) {
     return fail(FFTB_ERR_INVALID, "unexpected exception");
   }

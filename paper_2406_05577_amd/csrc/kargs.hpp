@@ -84,6 +84,7 @@ struct KArgs {
   const void* rootz_lo;
   const void* in;
   void* out;
+  const void* pot;      // inverse: real potential V[z][y][x] multiplied into the grid, or null
   void* col;            // column scratch
   double scale;         // 1/N for the forward direction
   unsigned int* counters;  // 24 work counters (persistent mode): 8 per kernel

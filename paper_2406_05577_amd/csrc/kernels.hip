@@ -243,11 +243,13 @@ __device__ void k2_task(const KArgs& a, int t, cpx<T>* lds) {
           if (xi >= 0) return Yb[((xi * m + rb + line) << bcl) + bl];
           return cpx<T>{0, 0};
         };
+        const T* __restrict__ pot = reinterpret_cast<const T*>(a.pot);
         auto gdst = [=](int line, int x, int bl, cpx<T> v) {
           const int y = r + n1 * (rb + line);
           const int b = b0 + bl;
-          if (b < nb)
-            gout[(static_cast<int64_t>(z * ny + y) * nx + x) * nb + b] = v;
+          const int64_t p = static_cast<int64_t>(z * ny + y) * nx + x;
+          if (pot) v = cscale(v, pot[p]);  // fused real-space potential
+          if (b < nb) gout[p * nb + b] = v;
         };
         axis_run<S, T>(a.ax, nrows, twx, twxl, bcl, X0, X1, gsrc, gdst);
         __syncthreads();

@@ -311,17 +311,32 @@ __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S) {
     const bool valid = rest < nrest;
     const int rv = valid ? rest : 0;
     const int bl = rv & bmask, k2 = rv >> bcl;
+    const int y = r + n1 * k2;
+    const int b = b0 + bl;
+    // fused real-space step: the potential at the x this lane writes, requested
+    // before the transform so that its latency hides behind it
+    T vp[E];
+    if (a.pot) {
+      const T* __restrict__ vrow =
+          reinterpret_cast<const T*>(a.pot) + static_cast<int64_t>(z * ny + y) * nx;
+#pragma unroll
+      for (int k = 0; k < E; ++k) vp[k] = vrow[k + E * q];
+    }
     cpx<T> v[E];
 #pragma unroll
     for (int j = 0; j < E; ++j)
       v[j] = (valid && xs[j] >= 0) ? S[xs[j] * sx + (k2 << bcl) + bl] : cpx<T>{0, 0};
     line_fft<E, H, +1, T, MF>(v, ctx);
-    const int y = r + n1 * k2;
-    const int b = b0 + bl;
     if (valid && b < nb) {
       cpx<T>* row = gout + static_cast<int64_t>(z * ny + y) * nx * nb + b;
+      if (a.pot) {
+        // the grid receives V(x, y, z) * psi
 #pragma unroll
-      for (int k = 0; k < E; ++k) row[static_cast<int64_t>(k + E * q) * nb] = v[k];
+        for (int k = 0; k < E; ++k) row[static_cast<int64_t>(k + E * q) * nb] = cscale(v[k], vp[k]);
+      } else {
+#pragma unroll
+        for (int k = 0; k < E; ++k) row[static_cast<int64_t>(k + E * q) * nb] = v[k];
+      }
     }
   }
 }
@@ -667,11 +682,11 @@ __global__ void __launch_bounds__(512) k2r_kernel(const KArgs a) {
 #define FFTB_REG_SHAPES_F64(X) \
   X(4, 1) X(5, 1) X(6, 1) X(8, 1) X(9, 1) X(10, 1) X(12, 1) X(15, 1) X(16, 1) \
   X(5, 4) X(6, 4) X(4, 8) X(12, 8) X(16, 8) X(18, 8) X(20, 8) X(45, 4)       \
-  X(6, 16) X(8, 16) X(9, 16) X(10, 16)
+  X(6, 16) X(8, 16) X(9, 16) X(10, 16) X(16, 16)
 #define FFTB_REG_SHAPES_F32(X) \
   X(4, 1) X(5, 1) X(6, 1) X(8, 1) X(9, 1) X(10, 1) X(12, 1) X(15, 1) X(16, 1) \
   X(5, 4) X(6, 4) X(4, 8) X(12, 8) X(16, 8) X(18, 8) X(20, 8) X(45, 4)       \
-  X(6, 16) X(8, 16) X(9, 16) X(10, 16)
+  X(6, 16) X(8, 16) X(9, 16) X(10, 16) X(16, 16)
 
 bool reg_shape_supported(bool fp64, int E, int H) {
 #define FFTB_CHK(e, h) if (E == e && H == h) return true;

@@ -36,7 +36,8 @@ EXPORTS = [
     "fftb_plan_create", "fftb_sphere_to_grid", "fftb_grid_to_sphere", "fftb_plan_get_info",
     "fftb_plan_workspace_size", "fftb_plan_sphere_stats", "fftb_plan_sphere_columns",
     "fftb_plan_destroy", "fftb_status_string", "fftb_last_error",
-    "fftb_plan_set_profiling", "fftb_plan_get_profile",
+    "fftb_plan_set_profiling", "fftb_plan_get_profile", "fftb_apply_potential",
+    "fftb_plan_create_cuboid",
 ]
 
 
@@ -122,6 +123,11 @@ def lib() -> C.CDLL:
     L.fftb_sphere_to_grid.restype = C.c_int
     L.fftb_grid_to_sphere.argtypes = [vp, vp, vp, vp]
     L.fftb_grid_to_sphere.restype = C.c_int
+    L.fftb_apply_potential.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.fftb_apply_potential.restype = C.c_int
+    L.fftb_plan_create_cuboid.argtypes = [C.POINTER(vp), C.POINTER(C.c_int32), C.c_int32, C.c_int,
+                                          C.c_uint32, C.POINTER(Tuning_t), vp]
+    L.fftb_plan_create_cuboid.restype = C.c_int
     L.fftb_plan_get_info.argtypes = [vp, C.POINTER(Info_t)]
     L.fftb_plan_get_info.restype = C.c_int
     L.fftb_plan_workspace_size.argtypes = [vp, C.POINTER(C.c_size_t)]
@@ -207,6 +213,29 @@ class Plan:
         self.flags = flags
         self.info = self.get_info()
 
+    @classmethod
+    def cuboid(cls, dims: Sequence[int], nbands: int, dtype: str = "c128", flags: int = 0,
+               tuning: Optional[dict] = None, stream=None) -> "Plan":
+        """The batched cuboid 3D FFT: every grid point is a coefficient, both
+        buffers hold G[z][y][x][b] (fftb_plan_create_cuboid)."""
+        L = lib()
+        self = cls.__new__(cls)
+        n = int(dims[0]) * int(dims[1]) * int(dims[2])
+        self._maps = [np.arange(n, dtype=np.int32)]
+        d = (C.c_int32 * 3)(*[int(v) for v in dims])
+        tun = make_tuning(tuning) if tuning else None
+        self.dtype = dtype
+        self._h = C.c_void_p()
+        st = None if (flags & PLAN_HOST_ONLY) else _stream_ptr(stream)
+        _check(L.fftb_plan_create_cuboid(C.byref(self._h), d, int(nbands),
+                                         FFTB_C128 if dtype == "c128" else FFTB_C64, flags,
+                                         C.byref(tun) if tun is not None else None, st))
+        self.dims = tuple(int(v) for v in dims)
+        self.nbands = [int(nbands)]
+        self.flags = flags
+        self.info = self.get_info()
+        return self
+
     def get_info(self) -> dict:
         inf = Info_t()
         _check(lib().fftb_plan_get_info(self._h, C.byref(inf)))
@@ -278,6 +307,27 @@ class Plan:
         _check(lib().fftb_grid_to_sphere(self._h, grid.data_ptr(), sphere.data_ptr(),
                                          _stream_ptr(stream)))
         return sphere
+
+    def apply_potential(self, sphere, potential, grid=None, out=None, stream=None):
+        """c' = grid_to_sphere(V * sphere_to_grid(c)) for a real potential V
+        (N values in [z][y][x] order, float64 for c128 plans, float32 for c64),
+        fused into the inverse kernel. `grid` receives V * psi."""
+        import torch
+        self._check_tensor(sphere, self.info["sphere_elems"], "sphere")
+        rdt = torch.float64 if self.info["dtype"] == 0 else torch.float32
+        nx, ny, nz = self.info["dims"]
+        if not (potential.is_cuda and potential.dtype == rdt and potential.is_contiguous()
+                and potential.numel() == nx * ny * nz):
+            raise ValueError(f"potential must be a contiguous {rdt} CUDA tensor of {nx * ny * nz} values")
+        if grid is None:
+            grid = torch.empty(self.info["grid_elems"], dtype=self.torch_dtype, device=sphere.device)
+        self._check_tensor(grid, self.info["grid_elems"], "grid")
+        if out is None:
+            out = torch.empty(self.info["sphere_elems"], dtype=self.torch_dtype, device=sphere.device)
+        self._check_tensor(out, self.info["sphere_elems"], "sphere")
+        _check(lib().fftb_apply_potential(self._h, sphere.data_ptr(), potential.data_ptr(),
+                                          grid.data_ptr(), out.data_ptr(), _stream_ptr(stream)))
+        return out
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:

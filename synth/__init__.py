@@ -127,6 +127,7 @@ class Workload:
 #   c3alt  c1 shapes with 256 bands in complex64
 #   c4     96^3, 8 k-points in [-0.5,0.5)^3, |G+k|<=24, 64 bands each, complex64
 #   c5     144x160x180, ellipsoid semi-axes (36,40,45), 4 k-points, 128 bands each
+#   x1     256^3, |G|<=64 (the paper's experiment shape), Gamma, 256 bands, complex128
 RECIPES = {
     "c1":    dict(dims=(32, 32, 32), semi=(8, 8, 8), nk=0, nb=4, dtype="c128", cidx=1, scale=False),
     "c2":    dict(dims=(128, 128, 128), semi=(32, 32, 32), nk=0, nb=256, dtype="c128", cidx=2, scale=True),
@@ -134,6 +135,8 @@ RECIPES = {
     "c3alt": dict(dims=(32, 32, 32), semi=(8, 8, 8), nk=0, nb=256, dtype="c64", cidx=3, scale=False),
     "c4":    dict(dims=(96, 96, 96), semi=(24, 24, 24), nk=8, nb=64, dtype="c64", cidx=4, scale=False),
     "c5":    dict(dims=(144, 160, 180), semi=(36, 40, 45), nk=4, nb=128, dtype="c64", cidx=5, scale=False),
+    # the paper's experiment shape (Section 4.1): 256^3 grid, sphere diameter 128, 256 bands
+    "x1":    dict(dims=(256, 256, 256), semi=(64, 64, 64), nk=0, nb=256, dtype="c128", cidx=6, scale=True),
 }
 
 

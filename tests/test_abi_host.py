@@ -135,6 +135,10 @@ def test_null_pointers():
     assert L.fftb_plan_get_info(None, C.byref(info)) == pk.FFTB_ERR_INVALID
     assert L.fftb_plan_get_info(h, None) == pk.FFTB_ERR_INVALID
     assert L.fftb_plan_sphere_stats(h, 5, None, None) == pk.FFTB_ERR_INVALID
+    assert L.fftb_apply_potential(None, None, None, None, None, None) == pk.FFTB_ERR_INVALID
+    assert L.fftb_apply_potential(h, C.c_void_p(16), None, C.c_void_p(16), C.c_void_p(16),
+                                  None) == pk.FFTB_ERR_INVALID
+    assert b"potential" in L.fftb_last_error()
     assert L.fftb_plan_destroy(h) == 0
     assert L.fftb_plan_destroy(None) == 0
 
@@ -163,3 +167,17 @@ def test_mfma_flag_validation():
     _expect_status(pk.FFTB_ERR_UNSUPPORTED,
                    lambda: pk.Plan((96, 16, 96), [lin2], 16, dtype="c64",
                                    flags=pk.PLAN_HOST_ONLY | pk.PLAN_MFMA))
+
+
+def test_cuboid_plan_tables():
+    """The batched cuboid transform: every grid point is a coefficient."""
+    dims = (12, 10, 6)
+    p = pk.Plan.cuboid(dims, 3, flags=pk.PLAN_HOST_ONLY)
+    n = dims[0] * dims[1] * dims[2]
+    assert p.info["total_coeffs"] == n
+    assert p.info["sphere_elems"] == p.info["grid_elems"] == n * 3
+    assert p.info["total_columns"] == dims[0] * dims[1]
+    assert p.info["max_slab"] == dims[0]
+    _expect_status(pk.FFTB_ERR_INVALID, lambda: pk.Plan.cuboid((12, 0, 6), 3, flags=pk.PLAN_HOST_ONLY))
+    _expect_status(pk.FFTB_ERR_INVALID, lambda: pk.Plan.cuboid(dims, 0, flags=pk.PLAN_HOST_ONLY))
+    _expect_status(pk.FFTB_ERR_UNSUPPORTED, lambda: pk.Plan.cuboid((14, 10, 6), 3, flags=pk.PLAN_HOST_ONLY))

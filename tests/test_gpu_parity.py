@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import synth
-from gpu_util import TOL, check_workload
+from gpu_util import TOL, check_workload, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -168,6 +168,88 @@ def test_full_cube_map(dtype):
     dt = np.complex128 if dtype == "c128" else np.complex64
     w = synth.Workload(name="cube", dims=dims, spheres=[synth.Sphere(m=m, lin=lin, kpt=(0, 0, 0), nbands=nb)],
                        coeffs=[c.astype(dt)], dtype=np.dtype(dt), seed=4)
+    e = check_workload(w, dtype)
+    assert max(e) <= TOL[dtype], e
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("flags", [0, 1, 5])
+@pytest.mark.parametrize("case", [0, 1])
+def test_apply_potential(case, flags, dtype):
+    """Fused real-space step c' = grid_to_sphere(V * sphere_to_grid(c)) against
+    the oracle, twice in a row (graph / persistent replays), for several
+    spheres sharing one potential; the work grid holds V * psi."""
+    import oracle
+    import torch
+    from gpu_util import make_plan, to_device, split_grid, split_sphere
+    dims, semi, kpts, nb, seed = (CASES[5] if case == 0 else REG_CASES[1])
+    w = synth.small_workload(dims, semi, kpts, nb, seed=seed, shuffle=True)
+    nx, ny, nz = dims
+    npdt = np.complex128 if dtype == "c128" else np.complex64
+    rdt = np.float64 if dtype == "c128" else np.float32
+    v = np.random.default_rng(77).standard_normal((nz, ny, nx)).astype(rdt)
+    coeffs = [c.astype(npdt) for c in w.coeffs]
+    p = make_plan(w, dtype=dtype, flags=flags)
+    sph = to_device(np.concatenate([c.reshape(-1) for c in coeffs]), dtype)
+    vt = torch.from_numpy(v.reshape(-1)).to("cuda")
+    grid = torch.empty(p.info["grid_elems"], dtype=sph.dtype, device="cuda")
+    for _ in range(2):
+        out = p.apply_potential(sph, vt, grid=grid)
+        torch.cuda.synchronize()
+        got = split_sphere(w, out.cpu().numpy())
+        gg = split_grid(w, grid.cpu().numpy())
+        for s, c, o, g in zip(w.spheres, coeffs, got, gg):
+            c64 = c.astype(np.complex128)
+            ref = oracle.apply_potential(dims, s.lin, c64, v.astype(np.float64))
+            assert rel(o, ref) <= TOL[dtype], (rel(o, ref), dtype, flags)
+            gref = oracle.sphere_to_grid(dims, s.lin, c64) * v.astype(np.float64)[..., None]
+            assert rel(g, gref) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_cuboid_plan(dtype):
+    """fftb_plan_create_cuboid: the batched 3D FFT of cuboid grids, against
+    the oracle with the whole grid as the map (and both directions)."""
+    import oracle
+    import torch
+    from gpu_util import to_device
+    from paper_2406_05577_amd import Plan
+    dims, nb = (24, 20, 18), 5
+    nx, ny, nz = dims
+    n = nx * ny * nz
+    rng = np.random.default_rng(21)
+    npdt = np.complex128 if dtype == "c128" else np.complex64
+    a = (rng.standard_normal((n, nb)) + 1j * rng.standard_normal((n, nb))).astype(npdt)
+    p = Plan.cuboid(dims, nb, dtype=dtype)
+    g = p.sphere_to_grid(to_device(a, dtype))
+    back = p.grid_to_sphere(g)
+    torch.cuda.synchronize()
+    lin = np.arange(n)
+    ref = oracle.sphere_to_grid(dims, lin, a.astype(np.complex128))
+    assert rel(g.cpu().numpy().reshape(nz, ny, nx, nb), ref) <= TOL[dtype]
+    assert rel(back.cpu().numpy().reshape(n, nb), a.astype(np.complex128)) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("dims", [(1, 6, 10), (8, 1, 9), (10, 6, 1), (1, 1, 12)])
+def test_degenerate_dims(dims, dtype):
+    """Grids with an axis of length 1 (a plane, a line): the transforms along
+    that axis are the identity."""
+    semi = tuple(max(d / 3.0, 0.5) for d in dims)
+    w = synth.small_workload(dims, semi, [(0.0, 0.0, 0.0)], 3, seed=31)
+    e = check_workload(w, dtype)
+    assert max(e) <= TOL[dtype], e
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_single_coefficient_sphere(dtype):
+    """Ns = 1 (only G = 0): the grid is constant, the round trip exact."""
+    lin = np.array([0], np.int32)
+    dims = (12, 10, 8)
+    c = synth.draw_coefficients(np.random.default_rng(8), 1, 4)
+    dt = np.complex128 if dtype == "c128" else np.complex64
+    w = synth.Workload(name="one", dims=dims, spheres=[synth.Sphere(m=np.zeros((1, 3), np.int64), lin=lin,
+                       kpt=(0, 0, 0), nbands=4)], coeffs=[c.astype(dt)], dtype=np.dtype(dt), seed=8)
     e = check_workload(w, dtype)
     assert max(e) <= TOL[dtype], e
 
