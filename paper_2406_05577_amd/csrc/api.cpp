@@ -212,8 +212,10 @@ size_t plane_lds_reg(const fftb_plan_s& P, int m, int bc, bool acc, int& sx, int
   return static_cast<size_t>(S + A) * es_of(P.dtype);
 }
 
-// Slots of the padded layout stay below 2^21 (they are packed with the block index).
-bool fold_slots_fit(const fftb_plan_s& P, int M) {
+// Slots of the padded layout stay below 2^21 (they are packed with the block
+// index), and one plane of the column scratch below 2 GiB (the fold addresses
+// it with 32-bit buffer offsets).
+bool fold_slots_fit(const fftb_plan_s& P, int M, int bc) {
   for (auto& s : P.sph) {
     int64_t slots = 0;
     for (int xi = 0; xi < s.nslab; ++xi) {
@@ -225,6 +227,8 @@ bool fold_slots_fit(const fftb_plan_s& P, int M) {
         }
     }
     if (slots >= (int64_t{1} << 21)) return false;
+    const int64_t nbp = static_cast<int64_t>((s.nb + bc - 1) / bc) * bc;
+    if (slots * nbp * es_of(P.dtype) >= (int64_t{1} << 31)) return false;
   }
   return true;
 }
@@ -346,7 +350,7 @@ fftb_status choose_dir(fftb_plan_s& P, int d, const fftb_dir_tuning& t) {
       // prefer a class length with a compiled register fold
       pick_classes(true, false);
       if (!D.reg2) pick_classes(false, false);
-      D.fold_m = D.reg2 && fold_m_supported(h2, D.m) && D.n1 <= 1024 && fold_slots_fit(P, D.m)
+      D.fold_m = D.reg2 && fold_m_supported(h2, D.m) && D.n1 <= 1024 && fold_slots_fit(P, D.m, D.bc)
                      ? D.m : 0;
       if (D.reg2 && !D.fold_m) {
         // the generic fold needs no staged tables
@@ -762,6 +766,19 @@ KArgs make_args(const fftb_plan_s& P, const DirCfg& D, const void* in, void* out
   a.nsplit = D.nsplit;
   a.fwd_cls = D.fwd_cls ? 1 : 0;
   a.g2 = D.reg2 ? (D.class_par ? D.n1 : D.nsplit) : 1;
+  // 32-bit buffer addressing where every region it covers allows it
+  a.plane32 = 1;
+  a.k1buf = 1;
+  const int64_t es = es_of(P.dtype);
+  for (size_t i = 0; i < P.sph.size(); ++i) {
+    const auto& sp = P.sph[i];
+    const int64_t nbp = static_cast<int64_t>(D.desc[i].nchunk) * D.bc;
+    const int64_t colplane = static_cast<int64_t>(D.desc[i].npcol) * nbp * es;
+    const int64_t zplane = static_cast<int64_t>(sp.nslab) * P.ny * nbp * es;
+    const int64_t gplane = static_cast<int64_t>(P.nx) * P.ny * sp.nb * es;
+    if (std::max(colplane, std::max(zplane, gplane)) >= (int64_t{1} << 31)) a.plane32 = 0;
+    if (sp.ns * sp.nb * es >= 0xffffffffLL || colplane * P.nz >= 0xffffffffLL) a.k1buf = 0;
+  }
   a.splits = D.d_splits;
   fill_axis(P.ax, a.ax);
   fill_axis(D.ay, a.ay);

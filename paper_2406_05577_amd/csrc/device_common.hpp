@@ -56,6 +56,44 @@ template <typename T>
 __device__ __forceinline__ cpx<T> cscale(cpx<T> a, T s) { return {a.re * s, a.im * s}; }
 __device__ __forceinline__ float ffma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double ffma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+// Raw buffer loads from a wave-uniform base: the lane supplies one 32-bit byte
+// offset and each load adds a uniform byte offset held in a scalar register,
+// so a strided run of loads needs a single address register instead of one
+// 64-bit address per load. Reads past the 4 GiB range return zero.
+// `base` must be the same in every lane of the wave (it is read from the first).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base) {
+  const uint64_t pa = reinterpret_cast<uint64_t>(base);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(pa));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(pa >> 32));
+  void* p = reinterpret_cast<void*>((static_cast<uint64_t>(hi) << 32) | lo);
+  // gfx9 raw buffer: no stride, full 32-bit range, dword 3 = 0x00020000
+  return __builtin_amdgcn_make_buffer_rsrc(p, static_cast<short>(0),
+                                           static_cast<int>(0xffffffffu), 0x00020000);
+}
+__device__ __forceinline__ cpx<double> buf_load(__amdgpu_buffer_rsrc_t r, const cpx<double>*,
+                                                unsigned voff, unsigned soff) {
+  typedef int v4i __attribute__((ext_vector_type(4)));
+  const v4i x = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+  return __builtin_bit_cast(cpx<double>, x);
+}
+__device__ __forceinline__ cpx<float> buf_load(__amdgpu_buffer_rsrc_t r, const cpx<float>*,
+                                               unsigned voff, unsigned soff) {
+  typedef int v2i __attribute__((ext_vector_type(2)));
+  const v2i x = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+  return __builtin_bit_cast(cpx<float>, x);
+}
+
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, cpx<double> v, unsigned voff,
+                                          unsigned soff) {
+  typedef int v4i __attribute__((ext_vector_type(4)));
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4i, v), r, voff, soff, 0);
+}
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, cpx<float> v, unsigned voff,
+                                          unsigned soff) {
+  typedef int v2i __attribute__((ext_vector_type(2)));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2i, v), r, voff, soff, 0);
+}
+
 // u + v*w with fused multiply-adds
 template <typename T>
 __device__ __forceinline__ cpx<T> cmac(cpx<T> u, cpx<T> v, cpx<T> w) {

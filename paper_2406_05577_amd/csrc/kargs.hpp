@@ -56,6 +56,9 @@ struct KArgs {
   int nsplit;        // forward plane tasks per (plane, chunk): slab ranges with their columns
   int fwd_cls;       // forward: class partials Z[z][xi][j][r], combined into columns by K3
   int g2;            // plane-kernel tasks per L2-sharing group (scheduling)
+  int plane32;       // every per-plane region (grid plane, column plane, class
+                     // partials of a plane) spans less than 2 GiB
+  int k1buf;         // every sphere's coefficients and column region span less than 4 GiB
   AxisDev ax, ay, az;
   const SphereDesc* sph;
   const int32_t* gidx;

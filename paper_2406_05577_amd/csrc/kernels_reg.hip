@@ -80,6 +80,15 @@ __device__ void k1r_task(const KArgs& a, int t) {
   // loads of all of them are issued before any is used
   constexpr int NP = (E <= 10 && !MF) ? 2 : 1;
   const int q = bitrev_bits(h, L);
+  // with a.k1buf the sphere and the column region are addressed as buffers
+  // (both below 4 GiB): one offset register per line, uniform z strides
+  constexpr unsigned es = sizeof(cpx<T>);
+  const unsigned nbp_es = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(nbp) * es);
+  const unsigned zstep_out = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(npcol) * nbp_es);
+  const unsigned zstep_in = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(H * npcol) * nbp_es);
+  const __amdgpu_buffer_rsrc_t rcol = buf_rsrc(colbuf);
+  const __amdgpu_buffer_rsrc_t rsph =
+      buf_rsrc(reinterpret_cast<const cpx<T>*>(S > 0 ? a.in : a.out) + d.sph_off);
   for (int it0 = threadIdx.x; it0 < iters; it0 += NP * blockDim.x) {
     bool ok[NP];
     int cc[NP], slot[NP], bls[NP];
@@ -105,35 +114,69 @@ __device__ void k1r_task(const KArgs& a, int t) {
 #pragma unroll
       for (int p = 0; p < NP; ++p) {
         const int b = b0 + bls[p];
+        if (a.k1buf) {
 #pragma unroll
-        for (int j = 0; j < E; ++j)
-          v[p][j] = (ok[p] && g[p][j] >= 0 && b < nb) ? in[static_cast<int64_t>(g[p][j]) * nb + b]
-                                                       : cpx<T>{0, 0};
+          for (int j = 0; j < E; ++j)
+            v[p][j] = (ok[p] && g[p][j] >= 0 && b < nb)
+                          ? buf_load(rsph, in, static_cast<unsigned>(g[p][j] * nb + b) * es, 0)
+                          : cpx<T>{0, 0};
+        } else {
+#pragma unroll
+          for (int j = 0; j < E; ++j)
+            v[p][j] = (ok[p] && g[p][j] >= 0 && b < nb) ? in[static_cast<int64_t>(g[p][j]) * nb + b]
+                                                         : cpx<T>{0, 0};
+        }
       }
     } else {
+      if (a.k1buf) {
 #pragma unroll
-      for (int p = 0; p < NP; ++p)
+        for (int p = 0; p < NP; ++p) {
+          const unsigned off = static_cast<unsigned>(h * npcol + slot[p]) * nbp_es + bls[p] * es;
 #pragma unroll
-        for (int j = 0; j < E; ++j)
-          v[p][j] = ok[p] ? colbuf[(static_cast<int64_t>(h + H * j) * npcol + slot[p]) * nbp + bls[p]]
-                          : cpx<T>{0, 0};
+          for (int j = 0; j < E; ++j)
+            v[p][j] = ok[p] ? buf_load(rcol, colbuf, off, j * zstep_in) : cpx<T>{0, 0};
+        }
+      } else {
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+          for (int j = 0; j < E; ++j)
+            v[p][j] = ok[p] ? colbuf[(static_cast<int64_t>(h + H * j) * npcol + slot[p]) * nbp + bls[p]]
+                            : cpx<T>{0, 0};
+      }
     }
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
       line_fft<E, H, S, T, MF>(v[p], ctx);
       if (!ok[p]) continue;
       if constexpr (S > 0) {
+        if (a.k1buf) {
+          const unsigned off =
+              static_cast<unsigned>(E * q * npcol + slot[p]) * nbp_es + bls[p] * es;
 #pragma unroll
-        for (int k = 0; k < E; ++k)
-          colbuf[(static_cast<int64_t>(k + E * q) * npcol + slot[p]) * nbp + bls[p]] = v[p][k];
+          for (int k = 0; k < E; ++k) buf_store(rcol, v[p][k], off, k * zstep_out);
+        } else {
+#pragma unroll
+          for (int k = 0; k < E; ++k)
+            colbuf[(static_cast<int64_t>(k + E * q) * npcol + slot[p]) * nbp + bls[p]] = v[p][k];
+        }
       } else {
         cpx<T>* __restrict__ out = reinterpret_cast<cpx<T>*>(a.out) + d.sph_off;
         const T sc = static_cast<T>(a.scale);
         const int b = b0 + bls[p];
+        if (a.k1buf) {
 #pragma unroll
-        for (int k = 0; k < E; ++k) {
-          const int g = gidx[cc[p] * nz + k + E * q];
-          if (g >= 0 && b < nb) out[static_cast<int64_t>(g) * nb + b] = cscale(v[p][k], sc);
+          for (int k = 0; k < E; ++k) {
+            const int g = gidx[cc[p] * nz + k + E * q];
+            if (g >= 0 && b < nb)
+              buf_store(rsph, cscale(v[p][k], sc), static_cast<unsigned>(g * nb + b) * es, 0);
+          }
+        } else {
+#pragma unroll
+          for (int k = 0; k < E; ++k) {
+            const int g = gidx[cc[p] * nz + k + E * q];
+            if (g >= 0 && b < nb) out[static_cast<int64_t>(g) * nb + b] = cscale(v[p][k], sc);
+          }
         }
       }
     }
@@ -145,7 +188,7 @@ __device__ void k1r_task(const KArgs& a, int t) {
 // slots are laid out in zero-padded blocks of M consecutive y per slab; one
 // thread folds and transforms a whole (slab, band) line in registers.
 // M == 0: generic fold.
-template <typename T, int E, int H, bool MF, int M>
+template <typename T, int E, int H, bool MF, int M, bool POT>
 __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S) {
   constexpr int L = log2_const<H>();
   const int s = find_sphere_k2r(a, t);
@@ -197,6 +240,11 @@ __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S) {
     __syncthreads();
     // two blocks per round trip when their values fit the register budget
     constexpr bool kPair = M * sizeof(T) <= 64;
+    // the plane's column scratch as a buffer (the host keeps it below 2 GiB):
+    // a block's M loads share one offset register
+    const __amdgpu_buffer_rsrc_t rs = buf_rsrc(colp);
+    const unsigned slot_bytes =
+        __builtin_amdgcn_readfirstlane(static_cast<unsigned>(nbp) * sizeof(cpx<T>));
     const int32_t* __restrict__ order = a.slab_order + d.sl_off;
     const int nlines = nslab << bcl;
     for (int it = threadIdx.x; it < nlines; it += blockDim.x) {
@@ -220,25 +268,28 @@ __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S) {
           for (int k = 0; k < M; ++k) u[k] = cmac(u[k], v[k], w);
         }
       };
+      auto off_of = [&](int e) {
+        return static_cast<unsigned>((e >> 10) * nbp + bl) * static_cast<unsigned>(sizeof(cpx<T>));
+      };
       for (int i = 0; i < nh; i += (kPair ? 2 : 1)) {
         const int e0 = lst[i];
-        const cpx<T>* __restrict__ p0 = colp + static_cast<int64_t>(e0 >> 10) * nbp + bl;
+        const unsigned o0 = off_of(e0);
         cpx<T> v0[M];
         if constexpr (kPair) {
           const bool two = i + 1 < nh;
           const int e1 = two ? lst[i + 1] : e0;
-          const cpx<T>* __restrict__ p1 = colp + static_cast<int64_t>(e1 >> 10) * nbp + bl;
+          const unsigned o1 = off_of(e1);
           cpx<T> v1[M];
 #pragma unroll
           for (int k = 0; k < M; ++k) {
-            v0[k] = p0[static_cast<int64_t>(k) * nbp];
-            v1[k] = p1[static_cast<int64_t>(k) * nbp];
+            v0[k] = buf_load(rs, colp, o0, k * slot_bytes);
+            v1[k] = buf_load(rs, colp, o1, k * slot_bytes);
           }
           accumulate(v0, e0 & 1023, true);
           accumulate(v1, e1 & 1023, two);
         } else {
 #pragma unroll
-          for (int k = 0; k < M; ++k) v0[k] = p0[static_cast<int64_t>(k) * nbp];
+          for (int k = 0; k < M; ++k) v0[k] = buf_load(rs, colp, o0, k * slot_bytes);
           accumulate(v0, e0 & 1023, true);
         }
       }
@@ -297,7 +348,11 @@ __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S) {
   // x-IFFT of the class's rows, written to the grid. Lane h of a line keeps
   // the same h for every row, so its slab lookups are loaded once.
   cpx<T>* __restrict__ gout = reinterpret_cast<cpx<T>*>(a.out) + d.grid_off;
-  const int h = threadIdx.x % H;
+  // the lane position is made opaque here so that the line context below is
+  // formed per task instead of being hoisted out of the persistent loop, where
+  // it would stay live across the fold
+  int h = threadIdx.x % H;
+  asm volatile("" : "+v"(h));
   const int q = bitrev_bits(h, L);
   const auto ctx = line_ctx<E, H, +1, T>(h, rootx, rootx_lo);
   int xs[E];
@@ -307,6 +362,10 @@ __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S) {
   const int per_wave = 64 / H;
   const int nrest_p = MF ? (nrest + per_wave - 1) / per_wave * per_wave : nrest;
   const int rstep = blockDim.x / H;
+  // plane z of the grid (below 2 GiB when a.plane32 is set)
+  const __amdgpu_buffer_rsrc_t gplane = buf_rsrc(gout + static_cast<int64_t>(z) * ny * nx * nb);
+  const unsigned xstride =
+      __builtin_amdgcn_readfirstlane(static_cast<unsigned>(nb) * sizeof(cpx<T>));
   for (int rest = threadIdx.x / H; rest < nrest_p; rest += rstep) {
     const bool valid = rest < nrest;
     const int rv = valid ? rest : 0;
@@ -316,7 +375,7 @@ __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S) {
     // fused real-space step: the potential at the x this lane writes, requested
     // before the transform so that its latency hides behind it
     T vp[E];
-    if (a.pot) {
+    if constexpr (POT) {
       const T* __restrict__ vrow =
           reinterpret_cast<const T*>(a.pot) + static_cast<int64_t>(z * ny + y) * nx;
 #pragma unroll
@@ -327,13 +386,21 @@ __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S) {
     for (int j = 0; j < E; ++j)
       v[j] = (valid && xs[j] >= 0) ? S[xs[j] * sx + (k2 << bcl) + bl] : cpx<T>{0, 0};
     line_fft<E, H, +1, T, MF>(v, ctx);
-    if (valid && b < nb) {
-      cpx<T>* row = gout + static_cast<int64_t>(z * ny + y) * nx * nb + b;
-      if (a.pot) {
-        // the grid receives V(x, y, z) * psi
+    if constexpr (POT) {
+      // the grid receives V(x, y, z) * psi
 #pragma unroll
-        for (int k = 0; k < E; ++k) row[static_cast<int64_t>(k + E * q) * nb] = cscale(v[k], vp[k]);
+      for (int k = 0; k < E; ++k) v[k] = cscale(v[k], vp[k]);
+    }
+    if (valid && b < nb) {
+      if (a.plane32) {
+        // the plane as a buffer: one offset register per line, the x stride
+        // in a scalar register
+        const unsigned off =
+            static_cast<unsigned>((y * nx + E * q) * nb + b) * static_cast<unsigned>(sizeof(cpx<T>));
+#pragma unroll
+        for (int k = 0; k < E; ++k) buf_store(gplane, v[k], off, k * xstride);
       } else {
+        cpx<T>* row = gout + static_cast<int64_t>(z * ny + y) * nx * nb + b;
 #pragma unroll
         for (int k = 0; k < E; ++k) row[static_cast<int64_t>(k + E * q) * nb] = v[k];
       }
@@ -368,6 +435,10 @@ __device__ __forceinline__ void fwd_x_rows(const KArgs& a, const cpx<T>* __restr
   const int per_wave = 64 / H;
   const int nrest_p = MF ? (nrest + per_wave - 1) / per_wave * per_wave : nrest;
   const int rstep = blockDim.x / H;
+  // plane z of the grid as a buffer (below 2 GiB when a.plane32 is set)
+  const __amdgpu_buffer_rsrc_t gplane = buf_rsrc(gin + static_cast<int64_t>(z) * ny * nx * nb);
+  const unsigned hstride =
+      __builtin_amdgcn_readfirstlane(static_cast<unsigned>(H * nb) * sizeof(cpx<T>));
   for (int rest = threadIdx.x / H; rest < nrest_p; rest += rstep) {
     const bool valid = rest < nrest;
     const int rv = valid ? rest : 0;
@@ -376,10 +447,18 @@ __device__ __forceinline__ void fwd_x_rows(const KArgs& a, const cpx<T>* __restr
     const int b = b0 + bl;
     const bool ld = valid && b < nb;
     cpx<T> v[E];
-    const cpx<T>* row = gin + static_cast<int64_t>(z * ny + y) * nx * nb + b;
+    if (a.plane32) {
+      const unsigned off =
+          static_cast<unsigned>((y * nx + h) * nb + b) * static_cast<unsigned>(sizeof(cpx<T>));
 #pragma unroll
-    for (int j = 0; j < E; ++j)
-      v[j] = ld ? row[static_cast<int64_t>(h + H * j) * nb] : cpx<T>{0, 0};
+      for (int j = 0; j < E; ++j)
+        v[j] = ld ? buf_load(gplane, gin, off, j * hstride) : cpx<T>{0, 0};
+    } else {
+      const cpx<T>* row = gin + static_cast<int64_t>(z * ny + y) * nx * nb + b;
+#pragma unroll
+      for (int j = 0; j < E; ++j)
+        v[j] = ld ? row[static_cast<int64_t>(h + H * j) * nb] : cpx<T>{0, 0};
+    }
     line_fft<E, H, -1, T, MF>(v, ctx);
     if (!valid) continue;
 #pragma unroll
@@ -543,6 +622,11 @@ __device__ void k3r_task(const KArgs& a, int t) {
     // NP items per thread per round (two in FP32); the partials and the column
     // slots of all of them are requested before any of them is used
     constexpr int NP = sizeof(T) == 4 ? 2 : 1;
+    // with a.plane32 the plane's partials and columns are addressed as buffers
+    constexpr unsigned es = sizeof(cpx<T>);
+    const unsigned nbp_es = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(nbp) * es);
+    const __amdgpu_buffer_rsrc_t rz = buf_rsrc(zp);
+    const __amdgpu_buffer_rsrc_t rc = buf_rsrc(colp);
     for (int it0 = threadIdx.x; it0 < items; it0 += NP * blockDim.x) {
       cpx<T> u[NP][kMaxRadixDev];
       int cs[NP][kMaxRadixDev];
@@ -558,13 +642,24 @@ __device__ void k3r_task(const KArgs& a, int t) {
         const int xi = div_small(jx, m, inv_m);
         const int j = jx - xi * m;
         bls[p] = bl;
-        const cpx<T>* __restrict__ src = zp + (static_cast<int64_t>(xi) * ny + j * n1) * nbp + bl;
         const int32_t* __restrict__ crow = cidx + xi * ny + j;
+        if (a.plane32) {
+          const unsigned off = static_cast<unsigned>((xi * ny + j * n1) * nbp + bl) * es;
 #pragma unroll
-        for (int r = 0; r < kMaxRadixDev; ++r) {
-          if (r < n1) {
-            u[p][r] = src[r * nbp];
-            cs[p][r] = crow[r * m];
+          for (int r = 0; r < kMaxRadixDev; ++r) {
+            if (r < n1) {
+              u[p][r] = buf_load(rz, zp, off, r * nbp_es);
+              cs[p][r] = crow[r * m];
+            }
+          }
+        } else {
+          const cpx<T>* __restrict__ src = zp + (static_cast<int64_t>(xi) * ny + j * n1) * nbp + bl;
+#pragma unroll
+          for (int r = 0; r < kMaxRadixDev; ++r) {
+            if (r < n1) {
+              u[p][r] = src[r * nbp];
+              cs[p][r] = crow[r * m];
+            }
           }
         }
       }
@@ -572,9 +667,16 @@ __device__ void k3r_task(const KArgs& a, int t) {
       for (int p = 0; p < NP; ++p) {
         if (!ok[p]) continue;
         butterfly<-1>(n1, u[p]);
+        if (a.plane32) {
 #pragma unroll
-        for (int q = 0; q < kMaxRadixDev; ++q)
-          if (q < n1 && cs[p][q] >= 0) colp[static_cast<int64_t>(cs[p][q]) * nbp + bls[p]] = u[p][q];
+          for (int q = 0; q < kMaxRadixDev; ++q)
+            if (q < n1 && cs[p][q] >= 0)
+              buf_store(rc, u[p][q], static_cast<unsigned>(cs[p][q] * nbp + bls[p]) * es, 0);
+        } else {
+#pragma unroll
+          for (int q = 0; q < kMaxRadixDev; ++q)
+            if (q < n1 && cs[p][q] >= 0) colp[static_cast<int64_t>(cs[p][q]) * nbp + bls[p]] = u[p][q];
+        }
       }
     }
     return;
@@ -649,7 +751,9 @@ __global__ void __launch_bounds__(256) k1r_kernel(const KArgs a) {
 }
 
 // FC: forward tasks write class partials (compiled apart from the accumulating
-// forward so that neither variant's register allocation limits the other)
+// forward so that neither variant's register allocation limits the other);
+// inverse tasks multiply by the real-space potential (compiled apart so that
+// the plain transform carries no potential registers)
 template <int S, typename T, int E, int H, bool MF, bool FC, int M>
 __global__ void __launch_bounds__(512) k2r_kernel(const KArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -657,7 +761,7 @@ __global__ void __launch_bounds__(512) k2r_kernel(const KArgs a) {
   if (!a.persistent) {
     const int t = static_task_g(a.k2_tasks, a.g2);
     if (t >= 0) {
-      if constexpr (S > 0) k2r_inv_task<T, E, H, MF, M>(a, t, lds);
+      if constexpr (S > 0) k2r_inv_task<T, E, H, MF, M, FC>(a, t, lds);
       else if constexpr (FC) k2r_fwd_cls_task<T, E, H, MF>(a, t, lds);
       else k2r_fwd_task<T, E, H, MF>(a, t, lds);
     }
@@ -670,7 +774,7 @@ __global__ void __launch_bounds__(512) k2r_kernel(const KArgs a) {
     const int t = __builtin_amdgcn_readfirstlane(sh_task);
     __syncthreads();
     if (t < 0) break;
-    if constexpr (S > 0) k2r_inv_task<T, E, H, MF, M>(a, t, lds);
+    if constexpr (S > 0) k2r_inv_task<T, E, H, MF, M, FC>(a, t, lds);
     else if constexpr (FC) k2r_fwd_cls_task<T, E, H, MF>(a, t, lds);
     else k2r_fwd_task<T, E, H, MF>(a, t, lds);
     __syncthreads();
@@ -724,9 +828,18 @@ static hipError_t launch_one(int which, const KArgs& a, int grid, int threads, s
   }
   if constexpr (S < 0) {
     if (a.fwd_cls) return launch_k2<S, T, E, H, MF, true, 0>(a, grid, threads, lds, st);
-  } else if constexpr (fold_m_compiled(H, 8)) {
-    if (fold_m == 8) return launch_k2<S, T, E, H, MF, false, 8>(a, grid, threads, lds, st);
-    if (fold_m == 16) return launch_k2<S, T, E, H, MF, false, 16>(a, grid, threads, lds, st);
+  } else {
+    const bool pot = a.pot != nullptr;
+    if constexpr (fold_m_compiled(H, 8)) {
+      if (fold_m == 8)
+        return pot ? launch_k2<S, T, E, H, MF, true, 8>(a, grid, threads, lds, st)
+                   : launch_k2<S, T, E, H, MF, false, 8>(a, grid, threads, lds, st);
+      if (fold_m == 16)
+        return pot ? launch_k2<S, T, E, H, MF, true, 16>(a, grid, threads, lds, st)
+                   : launch_k2<S, T, E, H, MF, false, 16>(a, grid, threads, lds, st);
+    }
+    if (fold_m != 0) return hipErrorInvalidValue;
+    if (pot) return launch_k2<S, T, E, H, MF, true, 0>(a, grid, threads, lds, st);
   }
   if (fold_m != 0) return hipErrorInvalidValue;
   return launch_k2<S, T, E, H, MF, false, 0>(a, grid, threads, lds, st);
@@ -735,11 +848,12 @@ static hipError_t launch_one(int which, const KArgs& a, int grid, int threads, s
 template <int S, typename T, int E, int H, bool MF>
 static hipError_t attr_one(size_t lds) {
   hipError_t e = attr_k2<S, T, E, H, MF, false, 0>(lds);
-  if constexpr (S < 0) {
-    if (e == hipSuccess) e = attr_k2<S, T, E, H, MF, true, 0>(lds);
-  } else if constexpr (fold_m_compiled(H, 8)) {
+  if (e == hipSuccess) e = attr_k2<S, T, E, H, MF, true, 0>(lds);
+  if constexpr (S > 0 && fold_m_compiled(H, 8)) {
     if (e == hipSuccess) e = attr_k2<S, T, E, H, MF, false, 8>(lds);
     if (e == hipSuccess) e = attr_k2<S, T, E, H, MF, false, 16>(lds);
+    if (e == hipSuccess) e = attr_k2<S, T, E, H, MF, true, 8>(lds);
+    if (e == hipSuccess) e = attr_k2<S, T, E, H, MF, true, 16>(lds);
   }
   return e;
 }
