@@ -30,9 +30,9 @@ WORKLOADS = {
     "c3": ("c3", "c64", 0),
     "c1": ("c1", "c128", 0),
     "c3alt": ("c3alt", "c64", 0),
-    "c4": ("c4", "c64", 1 | 4),
+    "c4": ("c4", "c64", 1 | 2 | 4),
     "c4_fp64": ("c4", "c128", 0),
-    "c5": ("c5", "c64", 1 | 4),
+    "c5": ("c5", "c64", 1 | 2 | 4),
     "c5_fp64": ("c5", "c128", 0),
     "x1": ("x1", "c128", 0),
     "x1_fp32": ("x1", "c64", 0),
