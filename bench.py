@@ -193,8 +193,8 @@ def main():
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(bands shard across GPUs without any exchange; see the design notes). "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(bands would shard across GPUs without any exchange). "
               "Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
