@@ -218,8 +218,13 @@ __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S) {
     // w_ny^{+k*r} and the length-M IFFT, written once to S. The slab's block
     // list (slot << 10 | tb) and the roots w_n1^{+tb*r} are staged in LDS.
     int32_t* tl = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(S) + a.lds_tab);
-    int32_t* tn = tl + nslab * n1;
+    int32_t* tn = tl + ((nslab * n1 + 3) & ~3);  // 16-byte aligned regions
     cpx<T>* troot = reinterpret_cast<cpx<T>*>(tn + ((nslab + 3) & ~3));
+    // the class twiddles w_ny^{k*r}, k < M (hi, then lo for FP32)
+    cpx<T>* ttw = troot + 2 * n1;
+    cpx<T>* ttwl = ttw + M;
+    // the slab order (heaviest first)
+    int32_t* tord = reinterpret_cast<int32_t*>(ttwl + M);
     {
       const int32_t* __restrict__ blk = a.slab_blk + d.sl_off * n1;
       const int32_t* __restrict__ nblk = a.slab_nblk + d.sl_off;
@@ -236,6 +241,12 @@ __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S) {
           troot[2 * tb + 1] = wl;
         }
       }
+      for (int k = threadIdx.x; k < M; k += blockDim.x) {
+        ttw[k] = twf[k * r];
+        if constexpr (std::is_same<T, float>::value) ttwl[k] = twfl[k * r];
+      }
+      const int32_t* __restrict__ ord = a.slab_order + d.sl_off;
+      for (int i = threadIdx.x; i < nslab; i += blockDim.x) tord[i] = ord[i];
     }
     __syncthreads();
     // two blocks per round trip when their values fit the register budget
@@ -245,11 +256,10 @@ __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S) {
     const __amdgpu_buffer_rsrc_t rs = buf_rsrc(colp);
     const unsigned slot_bytes =
         __builtin_amdgcn_readfirstlane(static_cast<unsigned>(nbp) * sizeof(cpx<T>));
-    const int32_t* __restrict__ order = a.slab_order + d.sl_off;
     const int nlines = nslab << bcl;
     for (int it = threadIdx.x; it < nlines; it += blockDim.x) {
       const int bl = it & bmask;
-      const int xi = order[it >> bcl];
+      const int xi = tord[it >> bcl];
       const int nh = tn[xi];
       const int32_t* lst = tl + xi * n1;
       cpx<T> u[M];
@@ -294,7 +304,7 @@ __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S) {
         }
       }
 #pragma unroll
-      for (int k = 1; k < M; ++k) u[k] = twmul<+1>(u[k], twf, twfl, k * r);
+      for (int k = 1; k < M; ++k) u[k] = twmul<+1>(u[k], ttw, ttwl, k);
       dft<M, +1>(u);
       cpx<T>* line = S + xi * sx + bl;
 #pragma unroll
