@@ -234,13 +234,11 @@ bool fold_slots_fit(const fftb_plan_s& P, int M, int bc) {
 }
 
 // LDS of the inverse fold's staged tables: per slab n1 block entries and a
-// count, then n1 roots (hi and lo) of the class, its m twiddles (hi, lo) and
-// the slab order.
+// count, then n1 roots (hi and lo) of the class and its m twiddles.
 size_t fold_table_bytes(const fftb_plan_s& P, int n1) {
   const size_t ints = ((static_cast<size_t>(P.max_nslab) * n1 + 3) & ~size_t{3}) +
                       ((P.max_nslab + 3) & ~3);
-  return ints * 4 + static_cast<size_t>(2 * n1 + 2 * (P.ny / n1)) * es_of(P.dtype) +
-         static_cast<size_t>(P.max_nslab) * 4;
+  return ints * 4 + static_cast<size_t>(2 * n1 + P.ny / n1) * es_of(P.dtype);
 }
 
 // Cut a sphere's slabs into Q contiguous ranges with about equal column counts.

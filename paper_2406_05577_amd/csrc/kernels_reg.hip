@@ -221,10 +221,9 @@ __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S) {
     int32_t* tn = tl + ((nslab * n1 + 3) & ~3);  // 16-byte aligned regions
     cpx<T>* troot = reinterpret_cast<cpx<T>*>(tn + ((nslab + 3) & ~3));
     // the class twiddles w_ny^{k*r}, k < M (hi, then lo for FP32)
+    // FP64: the class twiddles w_ny^{k*r}, k < M (staging them measured
+    // slower for the FP32 hi/lo pairs, which keep reading the global table)
     cpx<T>* ttw = troot + 2 * n1;
-    cpx<T>* ttwl = ttw + M;
-    // the slab order (heaviest first)
-    int32_t* tord = reinterpret_cast<int32_t*>(ttwl + M);
     {
       const int32_t* __restrict__ blk = a.slab_blk + d.sl_off * n1;
       const int32_t* __restrict__ nblk = a.slab_nblk + d.sl_off;
@@ -241,12 +240,8 @@ __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S) {
           troot[2 * tb + 1] = wl;
         }
       }
-      for (int k = threadIdx.x; k < M; k += blockDim.x) {
-        ttw[k] = twf[k * r];
-        if constexpr (std::is_same<T, float>::value) ttwl[k] = twfl[k * r];
-      }
-      const int32_t* __restrict__ ord = a.slab_order + d.sl_off;
-      for (int i = threadIdx.x; i < nslab; i += blockDim.x) tord[i] = ord[i];
+      if constexpr (std::is_same<T, double>::value)
+        for (int k = threadIdx.x; k < M; k += blockDim.x) ttw[k] = twf[k * r];
     }
     __syncthreads();
     // two blocks per round trip when their values fit the register budget
@@ -256,10 +251,11 @@ __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S) {
     const __amdgpu_buffer_rsrc_t rs = buf_rsrc(colp);
     const unsigned slot_bytes =
         __builtin_amdgcn_readfirstlane(static_cast<unsigned>(nbp) * sizeof(cpx<T>));
+    const int32_t* __restrict__ order = a.slab_order + d.sl_off;
     const int nlines = nslab << bcl;
     for (int it = threadIdx.x; it < nlines; it += blockDim.x) {
       const int bl = it & bmask;
-      const int xi = tord[it >> bcl];
+      const int xi = order[it >> bcl];
       const int nh = tn[xi];
       const int32_t* lst = tl + xi * n1;
       cpx<T> u[M];
@@ -303,8 +299,13 @@ __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S) {
           accumulate(v0, e0 & 1023, true);
         }
       }
+      if constexpr (std::is_same<T, double>::value) {
 #pragma unroll
-      for (int k = 1; k < M; ++k) u[k] = twmul<+1>(u[k], ttw, ttwl, k);
+        for (int k = 1; k < M; ++k) u[k] = twmul<+1>(u[k], ttw, ttw, k);
+      } else {
+#pragma unroll
+        for (int k = 1; k < M; ++k) u[k] = twmul<+1>(u[k], twf, twfl, k * r);
+      }
       dft<M, +1>(u);
       cpx<T>* line = S + xi * sx + bl;
 #pragma unroll
