@@ -212,6 +212,15 @@ size_t plane_lds_reg(const fftb_plan_s& P, int m, int bc, bool acc, int& sx, int
   return static_cast<size_t>(S + A) * es_of(P.dtype);
 }
 
+// Element stride between band vectors in the column scratch and the class
+// partials: the band chunks of all bands, plus one 128-byte line when the
+// stride is a multiple of 256 bytes (runs of equal stride then spread over the
+// L2 channels instead of landing on one; measured 5 % per round trip at C2).
+int64_t band_stride(int64_t nb, int bc, int es) {
+  const int64_t n = (nb + bc - 1) / bc * bc;
+  return (n * es) % 256 == 0 ? n + 128 / es : n;
+}
+
 // Slots of the padded layout stay below 2^21 (they are packed with the block
 // index), and one plane of the column scratch below 2 GiB (the fold addresses
 // it with 32-bit buffer offsets).
@@ -227,7 +236,7 @@ bool fold_slots_fit(const fftb_plan_s& P, int M, int bc) {
         }
     }
     if (slots >= (int64_t{1} << 21)) return false;
-    const int64_t nbp = static_cast<int64_t>((s.nb + bc - 1) / bc) * bc;
+    const int64_t nbp = band_stride(s.nb, bc, es_of(P.dtype));
     if (slots * nbp * es_of(P.dtype) >= (int64_t{1} << 31)) return false;
   }
   return true;
@@ -587,6 +596,7 @@ void build_descs(fftb_plan_s& P, DirCfg& D) {
     d.nslab = s.nslab;
     d.nb = s.nb;
     d.nchunk = (s.nb + bc - 1) / bc;
+    d.nbp = static_cast<int32_t>(band_stride(s.nb, bc, es_of(P.dtype)));
     d.k1_start = k1;
     k1 += ((s.ncol + D.lc - 1) / D.lc) * d.nchunk;
     d.k1_end = k1;
@@ -603,8 +613,8 @@ void build_descs(fftb_plan_s& P, DirCfg& D) {
     d.zp_off = zoff;  // relative to the end of the column region, fixed up below
     soff += s.ns * s.nb;
     goff += N * s.nb;
-    coff += static_cast<int64_t>(d.nchunk) * bc * P.nz * d.npcol;
-    if (D.fwd_cls) zoff += static_cast<int64_t>(d.nchunk) * bc * P.nz * s.nslab * P.ny;
+    coff += static_cast<int64_t>(d.nbp) * P.nz * d.npcol;
+    if (D.fwd_cls) zoff += static_cast<int64_t>(d.nbp) * P.nz * s.nslab * P.ny;
     gi += s.ncol * P.nz;
     ci += s.nslab * P.ny;
     cm += s.ncol;
@@ -779,7 +789,7 @@ KArgs make_args(const fftb_plan_s& P, const DirCfg& D, const void* in, void* out
   const int64_t es = es_of(P.dtype);
   for (size_t i = 0; i < P.sph.size(); ++i) {
     const auto& sp = P.sph[i];
-    const int64_t nbp = static_cast<int64_t>(D.desc[i].nchunk) * D.bc;
+    const int64_t nbp = D.desc[i].nbp;
     const int64_t colplane = static_cast<int64_t>(D.desc[i].npcol) * nbp * es;
     const int64_t zplane = static_cast<int64_t>(sp.nslab) * P.ny * nbp * es;
     const int64_t gplane = static_cast<int64_t>(P.nx) * P.ny * sp.nb * es;

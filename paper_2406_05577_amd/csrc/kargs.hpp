@@ -31,6 +31,9 @@ struct SphereDesc {
   int32_t nslab;
   int32_t nb;
   int32_t nchunk;      // ceil(nb / band_chunk)
+  int32_t nbp;         // element stride between the band vectors of the column scratch and the
+                       // class partials: nchunk*band_chunk, plus one 128-byte line when that
+                       // is a multiple of 256 bytes (keeps strided runs off one L2 channel)
   int32_t k1_start, k1_end;  // task range of the column kernel
   int32_t k2_start, k2_end;  // task range of the plane kernel
   int32_t k3_start, k3_end;  // task range of the forward class combine

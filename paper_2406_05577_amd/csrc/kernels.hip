@@ -131,7 +131,7 @@ __device__ void k1_task(const KArgs& a, int t, cpx<T>* lds) {
   const cpx<T>* twlo = reinterpret_cast<const cpx<T>*>(a.twz_lo);
   cpx<T>* b_0 = lds;
   cpx<T>* b_1 = lds + ((a.lc * nz) << bcl);
-  const int64_t nbp = d.nchunk << bcl;  // padded band vector per (z, column)
+  const int64_t nbp = d.nbp;  // band vector stride per (z, column)
   if constexpr (S > 0) {
     const cpx<T>* __restrict__ in = reinterpret_cast<const cpx<T>*>(a.in) + d.sph_off;
     auto gsrc = [=](int line, int z, int bl) -> cpx<T> {
@@ -183,7 +183,7 @@ __device__ void k2_task(const KArgs& a, int t, cpx<T>* lds) {
   const int32_t* __restrict__ xinv = a.xinv + d.xinv_off;
   const int32_t* __restrict__ cxi = a.col_xi + d.colmeta_off;
   const int32_t* __restrict__ cy = a.col_y + d.colmeta_off;
-  const int64_t nbp = d.nchunk << bcl;
+  const int64_t nbp = d.nbp;
   cpx<T>* colp =
       reinterpret_cast<cpx<T>*>(a.col) + d.col_off + static_cast<int64_t>(z) * npcol * nbp + b0;
   const cpx<T>* twx = reinterpret_cast<const cpx<T>*>(a.twx);

@@ -66,7 +66,7 @@ __device__ void k1r_task(const KArgs& a, int t) {
   const int32_t* __restrict__ cslot = a.col_slot + d.colmeta_off;
   const int32_t* __restrict__ gidx = a.gidx + d.gidx_off;
   // column scratch: one padded band vector (nbp values) per (z, column slot)
-  const int nbp = d.nchunk << bcl;
+  const int nbp = d.nbp;
   cpx<T>* __restrict__ colbuf = reinterpret_cast<cpx<T>*>(a.col) + d.col_off + b0;
   const cpx<T>* rootz = reinterpret_cast<const cpx<T>*>(a.rootz);
   const cpx<T>* rootz_lo = reinterpret_cast<const cpx<T>*>(a.rootz_lo);
@@ -203,7 +203,7 @@ __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S) {
   const int nx = a.nx, ny = a.ny, sx = a.sx;
   const int nb = d.nb, npcol = d.npcol, nslab = d.nslab;
   const int32_t* __restrict__ xinv = a.xinv + d.xinv_off;
-  const int nbp = d.nchunk << bcl;
+  const int nbp = d.nbp;
   const cpx<T>* __restrict__ colp = reinterpret_cast<const cpx<T>*>(a.col) + d.col_off +
                                     static_cast<int64_t>(z) * npcol * nbp + b0;
   const cpx<T>* twf = reinterpret_cast<const cpx<T>*>(a.twf);
@@ -499,7 +499,7 @@ __device__ void k2r_fwd_cls_task(const KArgs& a, int t, cpx<T>* S) {
   const cpx<T>* __restrict__ gin = reinterpret_cast<const cpx<T>*>(a.in) + d.grid_off;
   const cpx<T>* twf = reinterpret_cast<const cpx<T>*>(a.twf);
   const cpx<T>* twfl = reinterpret_cast<const cpx<T>*>(a.twf_lo);
-  const int nbp = d.nchunk << bcl;
+  const int nbp = d.nbp;
   cpx<T>* __restrict__ zp = reinterpret_cast<cpx<T>*>(a.col) + d.zp_off +
                             (static_cast<int64_t>(z) * nslab * ny + r) * nbp + b0;
 
@@ -541,7 +541,7 @@ __device__ void k2r_fwd_task(const KArgs& a, int t, cpx<T>* S) {
   const int32_t* __restrict__ cxi = a.col_xi + d.colmeta_off;
   const int32_t* __restrict__ cslot = a.col_slot + d.colmeta_off;
   const int32_t* __restrict__ sst = a.slabstart + d.slab_off;
-  const int nbp = d.nchunk << bcl;
+  const int nbp = d.nbp;
   cpx<T>* __restrict__ colp = reinterpret_cast<cpx<T>*>(a.col) + d.col_off +
                               static_cast<int64_t>(z) * npcol * nbp + b0;
   const cpx<T>* __restrict__ gin = reinterpret_cast<const cpx<T>*>(a.in) + d.grid_off;
@@ -619,7 +619,7 @@ __device__ void k3r_task(const KArgs& a, int t) {
   const int b0 = chunk << bcl;
   const int ny = a.ny, n1 = a.n1, m = a.m;
   const int nslab = d.nslab, npcol = d.npcol;
-  const int nbp = d.nchunk << bcl;
+  const int nbp = d.nbp;
   const cpx<T>* __restrict__ zp = reinterpret_cast<const cpx<T>*>(a.col) + d.zp_off +
                                   static_cast<int64_t>(z) * nslab * ny * nbp + b0;
   cpx<T>* __restrict__ colp = reinterpret_cast<cpx<T>*>(a.col) + d.col_off +
