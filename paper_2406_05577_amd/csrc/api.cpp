@@ -461,10 +461,11 @@ fftb_status choose_dir(fftb_plan_s& P, int d, const fftb_dir_tuning& t) {
       return fail(FFTB_ERR_UNSUPPORTED, "no in-lane DFT_16 stage for the matrix cores in this plan");
   }
   if (D.reg2) {
-    // an inverse class slab that leaves room for one workgroup per CU: twice
-    // the waves per workgroup (measured faster for the FP32 configurations
-    // and the 96^3 FP64 one)
-    if (inverse && !t.threads && D.lds2 > kLdsMax / 2) D.threads = 512;
+    // a class slab that leaves room for one workgroup per CU: twice the waves
+    // per workgroup (measured faster for the inverse of the FP32
+    // configurations and the 96^3 FP64 one, and picked by the autotuner for
+    // both directions of the 144x160x180 one)
+    if (!t.threads && D.lds2 > kLdsMax / 2) D.threads = 512;
     return FFTB_OK;
   }
   // ---- plane kernel, LDS-stage path
