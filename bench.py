@@ -57,8 +57,9 @@ DESCR = {
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("kernels.hip", "kernels_reg.hip", "device_common.hpp", "kargs.hpp", "api.cpp", "plan.cpp"):
-        with open(os.path.join(ROOT, "paper_2406_05577_amd", "csrc", f), "rb") as fh:
+    csrc = os.path.join(ROOT, "paper_2406_05577_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 

@@ -1,738 +1,11 @@
-// Register-path kernels for gfx950. Each 1D transform line lives in the
-// registers of H adjacent lanes (E = n/H values per lane, DFT_E in registers,
-// DFT_H across the lanes), so the column kernel needs no LDS at all and the
-// plane kernel uses LDS only for the y-class slab (and, in the forward
-// direction, optionally for the column accumulators).
-//
-// Column kernel: z-transforms on the occupied (x,y) columns only (the padding
-// along z is fused with the transform, Section 2.2).
-// Plane kernel, inverse: task = (plane z, band chunk, y class r). The columns
-// of each occupied slab x are folded into the class (one decimation-in-
-// frequency stage evaluated for the single output class r), transformed along
-// y with length m = ny/n1, then every row y = r + n1*k2 is transformed along x
-// over the full grid and written. The n1 tasks of one (plane, chunk) are
-// consecutive, so the blocks on one XCD read the same column data from L2.
-// Plane kernel, forward, class-parallel (default): task = (plane z, band chunk,
-// y class r). The rows y = r + n1*k2 are transformed along x keeping the
-// occupied x only, then along y with length m; the result, multiplied by
-// w_ny^{-j*r}, is stored as the class partial Z_r[xi][j]. The combine kernel
-// then forms each column value y = j + m*t as the length-n1 DFT over the
-// classes, sum_r w_n1^{-t*r} Z_r[xi][j] (a decimation-in-time split of the
-// y transform), and the column kernel runs the z transforms.
-// Plane kernel, forward, accumulating: task = (plane z, band chunk, column
-// split); for each class r the split's columns accumulate the class's
-// contribution w_ny^{-y*r} * Y[xi][y mod m] in LDS or in global memory.
-#include <hip/hip_runtime.h>
-
-#include <type_traits>
-
-#include "device_common.hpp"
+// Register-path dispatch: shape tables and the launchers the host calls. The
+// kernels themselves are templates in kernels_reg.hpp, instantiated in the
+// reg_*.hip translation units.
+#include "kernels_reg.hpp"
 
 namespace fftb {
 
-
-__device__ __forceinline__ int find_sphere_k1r(const KArgs& a, int t) {
-  int s = 0;
-  while (s + 1 < a.nsph && t >= a.sph[s].k1_end) ++s;
-  return s;
-}
-__device__ __forceinline__ int find_sphere_k2r(const KArgs& a, int t) {
-  int s = 0;
-  while (s + 1 < a.nsph && t >= a.sph[s].k2_end) ++s;
-  return s;
-}
-
-// floor(n / d) for 0 <= n < 2^22 through a float reciprocal and one correction
-__device__ __forceinline__ int div_small(int n, int d, float inv_d) {
-  int q = static_cast<int>(static_cast<float>(n) * inv_d);
-  const int rem = n - q * d;
-  q += (rem >= d) - (rem < 0);
-  return q;
-}
-
-// ---------------------------------------------------------------------------
-template <int S, typename T, int E, int H, bool MF>
-__device__ void k1r_task(const KArgs& a, int t) {
-  constexpr int L = log2_const<H>();
-  const int s = find_sphere_k1r(a, t);
-  const SphereDesc d = a.sph[s];
-  const int lt = t - d.k1_start;
-  const int chunk = lt % d.nchunk, cb = lt / d.nchunk;
-  const int c0 = cb * a.lc;
-  const int nl = min(a.lc, d.ncol - c0);
-  const int bcl = a.bcl, bmask = (1 << bcl) - 1;
-  const int b0 = chunk << bcl;
-  const int nz = a.nz, nb = d.nb, npcol = d.npcol;
-  const int32_t* __restrict__ cslot = a.col_slot + d.colmeta_off;
-  const int32_t* __restrict__ gidx = a.gidx + d.gidx_off;
-  // column scratch: one padded band vector (nbp values) per (z, column slot)
-  const int nbp = d.nbp;
-  cpx<T>* __restrict__ colbuf = reinterpret_cast<cpx<T>*>(a.col) + d.col_off + b0;
-  const cpx<T>* rootz = reinterpret_cast<const cpx<T>*>(a.rootz);
-  const cpx<T>* rootz_lo = reinterpret_cast<const cpx<T>*>(a.rootz_lo);
-  const int items = (nl << bcl) * H;
-  // with the matrix-core codelet whole waves take part: pad to 64 lanes
-  const int iters = MF ? ((items + 63) & ~63) : items;
-  // the block size is a multiple of H: a thread keeps its lane position h
-  const int h = threadIdx.x % H;
-  const auto ctx = line_ctx<E, H, S, T>(h, rootz, rootz_lo);
-  // NP lines per thread per round (two for short lines): the table lookups and
-  // loads of all of them are issued before any is used
-  constexpr int NP = (E <= 10 && !MF) ? 2 : 1;
-  const int q = bitrev_bits(h, L);
-  // with a.k1buf the sphere and the column region are addressed as buffers
-  // (both below 4 GiB): one offset register per line, uniform z strides
-  constexpr unsigned es = sizeof(cpx<T>);
-  const unsigned nbp_es = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(nbp) * es);
-  const unsigned zstep_out = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(npcol) * nbp_es);
-  const unsigned zstep_in = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(H * npcol) * nbp_es);
-  const __amdgpu_buffer_rsrc_t rcol = buf_rsrc(colbuf);
-  const __amdgpu_buffer_rsrc_t rsph =
-      buf_rsrc(reinterpret_cast<const cpx<T>*>(S > 0 ? a.in : a.out) + d.sph_off);
-  for (int it0 = threadIdx.x; it0 < iters; it0 += NP * blockDim.x) {
-    bool ok[NP];
-    int cc[NP], slot[NP], bls[NP];
-    cpx<T> v[NP][E];
-#pragma unroll
-    for (int p = 0; p < NP; ++p) {
-      const int it = it0 + p * blockDim.x;
-      // with the matrix-core codelet padded lanes still run the transform
-      ok[p] = MF ? it < items : it < iters;
-      const int iv = ok[p] ? it : h;
-      const int rest = iv / H;
-      bls[p] = rest & bmask;
-      cc[p] = c0 + (rest >> bcl);
-      slot[p] = cslot[cc[p]];
-    }
-    if constexpr (S > 0) {
-      const cpx<T>* __restrict__ in = reinterpret_cast<const cpx<T>*>(a.in) + d.sph_off;
-      int g[NP][E];
-#pragma unroll
-      for (int p = 0; p < NP; ++p)
-#pragma unroll
-        for (int j = 0; j < E; ++j) g[p][j] = gidx[cc[p] * nz + h + H * j];
-#pragma unroll
-      for (int p = 0; p < NP; ++p) {
-        const int b = b0 + bls[p];
-        if (a.k1buf) {
-#pragma unroll
-          for (int j = 0; j < E; ++j)
-            v[p][j] = (ok[p] && g[p][j] >= 0 && b < nb)
-                          ? buf_load(rsph, in, static_cast<unsigned>(g[p][j] * nb + b) * es, 0)
-                          : cpx<T>{0, 0};
-        } else {
-#pragma unroll
-          for (int j = 0; j < E; ++j)
-            v[p][j] = (ok[p] && g[p][j] >= 0 && b < nb) ? in[static_cast<int64_t>(g[p][j]) * nb + b]
-                                                         : cpx<T>{0, 0};
-        }
-      }
-    } else {
-      if (a.k1buf) {
-#pragma unroll
-        for (int p = 0; p < NP; ++p) {
-          const unsigned off = static_cast<unsigned>(h * npcol + slot[p]) * nbp_es + bls[p] * es;
-#pragma unroll
-          for (int j = 0; j < E; ++j)
-            v[p][j] = ok[p] ? buf_load(rcol, colbuf, off, j * zstep_in) : cpx<T>{0, 0};
-        }
-      } else {
-#pragma unroll
-        for (int p = 0; p < NP; ++p)
-#pragma unroll
-          for (int j = 0; j < E; ++j)
-            v[p][j] = ok[p] ? colbuf[(static_cast<int64_t>(h + H * j) * npcol + slot[p]) * nbp + bls[p]]
-                            : cpx<T>{0, 0};
-      }
-    }
-#pragma unroll
-    for (int p = 0; p < NP; ++p) {
-      line_fft<E, H, S, T, MF>(v[p], ctx);
-      if (!ok[p]) continue;
-      if constexpr (S > 0) {
-        if (a.k1buf) {
-          const unsigned off =
-              static_cast<unsigned>(E * q * npcol + slot[p]) * nbp_es + bls[p] * es;
-#pragma unroll
-          for (int k = 0; k < E; ++k) buf_store(rcol, v[p][k], off, k * zstep_out);
-        } else {
-#pragma unroll
-          for (int k = 0; k < E; ++k)
-            colbuf[(static_cast<int64_t>(k + E * q) * npcol + slot[p]) * nbp + bls[p]] = v[p][k];
-        }
-      } else {
-        cpx<T>* __restrict__ out = reinterpret_cast<cpx<T>*>(a.out) + d.sph_off;
-        const T sc = static_cast<T>(a.scale);
-        const int b = b0 + bls[p];
-        if (a.k1buf) {
-#pragma unroll
-          for (int k = 0; k < E; ++k) {
-            const int g = gidx[cc[p] * nz + k + E * q];
-            if (g >= 0 && b < nb)
-              buf_store(rsph, cscale(v[p][k], sc), static_cast<unsigned>(g * nb + b) * es, 0);
-          }
-        } else {
-#pragma unroll
-          for (int k = 0; k < E; ++k) {
-            const int g = gidx[cc[p] * nz + k + E * q];
-            if (g >= 0 && b < nb) out[static_cast<int64_t>(g) * nb + b] = cscale(v[p][k], sc);
-          }
-        }
-      }
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// M > 0: the class length m = M is a compile-time constant and the column
-// slots are laid out in zero-padded blocks of M consecutive y per slab; one
-// thread folds and transforms a whole (slab, band) line in registers.
-// M == 0: generic fold.
-template <typename T, int E, int H, bool MF, int M, bool POT>
-__device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S) {
-  constexpr int L = log2_const<H>();
-  const int s = find_sphere_k2r(a, t);
-  const SphereDesc d = a.sph[s];
-  const int lt = t - d.k2_start;
-  const int n1 = a.n1, m = a.m;
-  const int r = lt % n1;
-  const int rest0 = lt / n1;
-  const int chunk = rest0 % d.nchunk, z = rest0 / d.nchunk;
-  const int bcl = a.bcl, bmask = (1 << bcl) - 1;
-  const int b0 = chunk << bcl;
-  const int nx = a.nx, ny = a.ny, sx = a.sx;
-  const int nb = d.nb, npcol = d.npcol, nslab = d.nslab;
-  const int32_t* __restrict__ xinv = a.xinv + d.xinv_off;
-  const int nbp = d.nbp;
-  const cpx<T>* __restrict__ colp = reinterpret_cast<const cpx<T>*>(a.col) + d.col_off +
-                                    static_cast<int64_t>(z) * npcol * nbp + b0;
-  const cpx<T>* twf = reinterpret_cast<const cpx<T>*>(a.twf);
-  const cpx<T>* twfl = reinterpret_cast<const cpx<T>*>(a.twf_lo);
-  const cpx<T>* rootx = reinterpret_cast<const cpx<T>*>(a.rootx);
-  const cpx<T>* rootx_lo = reinterpret_cast<const cpx<T>*>(a.rootx_lo);
-
-  if constexpr (M > 0) {
-    // per (slab, band) line, heaviest slabs first: for each block tb of M
-    // consecutive y (y = k + M*tb) holding a column of the slab, u[k] +=
-    // col(y) * w_n1^{+tb*r} (absent columns are zero slots); then u[k] *=
-    // w_ny^{+k*r} and the length-M IFFT, written once to S. The slab's block
-    // list (slot << 10 | tb) and the roots w_n1^{+tb*r} are staged in LDS.
-    int32_t* tl = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(S) + a.lds_tab);
-    int32_t* tn = tl + ((nslab * n1 + 3) & ~3);  // 16-byte aligned regions
-    cpx<T>* troot = reinterpret_cast<cpx<T>*>(tn + ((nslab + 3) & ~3));
-    // the class twiddles w_ny^{k*r}, k < M (hi, then lo for FP32)
-    // FP64: the class twiddles w_ny^{k*r}, k < M (staging them measured
-    // slower for the FP32 hi/lo pairs, which keep reading the global table)
-    cpx<T>* ttw = troot + 2 * n1;
-    {
-      const int32_t* __restrict__ blk = a.slab_blk + d.sl_off * n1;
-      const int32_t* __restrict__ nblk = a.slab_nblk + d.sl_off;
-      for (int i = threadIdx.x; i < nslab * n1; i += blockDim.x) tl[i] = blk[i];
-      for (int i = threadIdx.x; i < nslab; i += blockDim.x) tn[i] = nblk[i];
-      for (int tb = threadIdx.x; tb < n1; tb += blockDim.x) {
-        const int idx = M * ((tb * r) % n1);  // w_n1^{tb*r} = w_ny^{M*((tb*r) mod n1)}
-        cpx<T> w = twf[idx];
-        w.im = -w.im;
-        troot[2 * tb] = w;
-        if constexpr (std::is_same<T, float>::value) {
-          cpx<T> wl = twfl[idx];
-          wl.im = -wl.im;
-          troot[2 * tb + 1] = wl;
-        }
-      }
-      if constexpr (std::is_same<T, double>::value)
-        for (int k = threadIdx.x; k < M; k += blockDim.x) ttw[k] = twf[k * r];
-    }
-    __syncthreads();
-    // two blocks per round trip when their values fit the register budget
-    constexpr bool kPair = M * sizeof(T) <= 64;
-    // the plane's column scratch as a buffer (the host keeps it below 2 GiB):
-    // a block's M loads share one offset register
-    const __amdgpu_buffer_rsrc_t rs = buf_rsrc(colp);
-    const unsigned slot_bytes =
-        __builtin_amdgcn_readfirstlane(static_cast<unsigned>(nbp) * sizeof(cpx<T>));
-    const int32_t* __restrict__ order = a.slab_order + d.sl_off;
-    const int nlines = nslab << bcl;
-    for (int it = threadIdx.x; it < nlines; it += blockDim.x) {
-      const int bl = it & bmask;
-      const int xi = order[it >> bcl];
-      const int nh = tn[xi];
-      const int32_t* lst = tl + xi * n1;
-      cpx<T> u[M];
-#pragma unroll
-      for (int k = 0; k < M; ++k) u[k] = cpx<T>{0, 0};
-      auto accumulate = [&](const cpx<T>* v, int tb, bool use) {
-        cpx<T> w = troot[2 * tb];
-        if (!use) w = cpx<T>{0, 0};
-        if constexpr (std::is_same<T, float>::value) {
-          cpx<T> wl = troot[2 * tb + 1];
-          if (!use) wl = cpx<T>{0, 0};
-#pragma unroll
-          for (int k = 0; k < M; ++k) u[k] = cmac_hl(u[k], v[k], w, wl);
-        } else {
-#pragma unroll
-          for (int k = 0; k < M; ++k) u[k] = cmac(u[k], v[k], w);
-        }
-      };
-      auto off_of = [&](int e) {
-        return static_cast<unsigned>((e >> 10) * nbp + bl) * static_cast<unsigned>(sizeof(cpx<T>));
-      };
-      for (int i = 0; i < nh; i += (kPair ? 2 : 1)) {
-        const int e0 = lst[i];
-        const unsigned o0 = off_of(e0);
-        cpx<T> v0[M];
-        if constexpr (kPair) {
-          const bool two = i + 1 < nh;
-          const int e1 = two ? lst[i + 1] : e0;
-          const unsigned o1 = off_of(e1);
-          cpx<T> v1[M];
-#pragma unroll
-          for (int k = 0; k < M; ++k) {
-            v0[k] = buf_load(rs, colp, o0, k * slot_bytes);
-            v1[k] = buf_load(rs, colp, o1, k * slot_bytes);
-          }
-          accumulate(v0, e0 & 1023, true);
-          accumulate(v1, e1 & 1023, two);
-        } else {
-#pragma unroll
-          for (int k = 0; k < M; ++k) v0[k] = buf_load(rs, colp, o0, k * slot_bytes);
-          accumulate(v0, e0 & 1023, true);
-        }
-      }
-      if constexpr (std::is_same<T, double>::value) {
-#pragma unroll
-        for (int k = 1; k < M; ++k) u[k] = twmul<+1>(u[k], ttw, ttw, k);
-      } else {
-#pragma unroll
-        for (int k = 1; k < M; ++k) u[k] = twmul<+1>(u[k], twf, twfl, k * r);
-      }
-      dft<M, +1>(u);
-      cpx<T>* line = S + xi * sx + bl;
-#pragma unroll
-      for (int k = 0; k < M; ++k) line[k << bcl] = u[k];
-    }
-    __syncthreads();
-  } else {
-    const int32_t* __restrict__ cidx = a.colidx + d.colidx_off;
-
-    // fold, one output per thread:
-    //   F_r[xi][j] = w_ny^{+j*r} * sum_t col(xi, y = j + m*t) * w_n1^{+t*r}
-    // (the first stage of a decimation-in-frequency split of the y transform,
-    // evaluated for the single output class r; absent columns are zero)
-    const int mr = m * r;  // w_n1^{t*r} = w_ny^{m*t*r}
-    const float inv_m = 1.0f / static_cast<float>(m);
-    const int nfold = (nslab * m) << bcl;
-    for (int it = threadIdx.x; it < nfold; it += blockDim.x) {
-      const int bl = it & bmask;
-      const int jx = it >> bcl;
-      const int xi = div_small(jx, m, inv_m);
-      const int j = jx - xi * m;
-      const int32_t* __restrict__ crow = cidx + xi * ny + j;
-      cpx<T> acc{0, 0};
-      int idx = 0;
-  #pragma unroll 4
-      for (int tt = 0; tt < n1; ++tt) {
-        const int ci = crow[tt * m];
-        if (ci >= 0) acc = cadd(acc, twmul<+1>(colp[static_cast<int64_t>(ci) * nbp + bl], twf, twfl, idx));
-        idx += mr;
-        if (idx >= ny) idx -= ny;
-      }
-      S[xi * sx + (j << bcl) + bl] = twmul<+1>(acc, twf, twfl, j * r);
-    }
-    __syncthreads();
-    // y-IFFT of length m per (slab, band) line, in place
-    const int nlines = nslab << bcl;
-    for (int it = threadIdx.x; it < nlines; it += blockDim.x) {
-      const int bl = it & bmask, xi = it >> bcl;
-      cpx<T>* line = S + xi * sx + bl;
-      cpx<T> u[kMaxRadixDev];
-  #pragma unroll
-      for (int j = 0; j < kMaxRadixDev; ++j)
-        if (j < m) u[j] = line[j << bcl];
-      butterfly<+1>(m, u);
-  #pragma unroll
-      for (int j = 0; j < kMaxRadixDev; ++j)
-        if (j < m) line[j << bcl] = u[j];
-    }
-    __syncthreads();
-  }
-  // x-IFFT of the class's rows, written to the grid. Lane h of a line keeps
-  // the same h for every row, so its slab lookups are loaded once.
-  cpx<T>* __restrict__ gout = reinterpret_cast<cpx<T>*>(a.out) + d.grid_off;
-  // the lane position is made opaque here so that the line context below is
-  // formed per task instead of being hoisted out of the persistent loop, where
-  // it would stay live across the fold
-  int h = threadIdx.x % H;
-  asm volatile("" : "+v"(h));
-  const int q = bitrev_bits(h, L);
-  const auto ctx = line_ctx<E, H, +1, T>(h, rootx, rootx_lo);
-  int xs[E];
-#pragma unroll
-  for (int j = 0; j < E; ++j) xs[j] = xinv[h + H * j];
-  const int nrest = m << bcl;
-  const int per_wave = 64 / H;
-  const int nrest_p = MF ? (nrest + per_wave - 1) / per_wave * per_wave : nrest;
-  const int rstep = blockDim.x / H;
-  // plane z of the grid (below 2 GiB when a.plane32 is set)
-  const __amdgpu_buffer_rsrc_t gplane = buf_rsrc(gout + static_cast<int64_t>(z) * ny * nx * nb);
-  const unsigned xstride =
-      __builtin_amdgcn_readfirstlane(static_cast<unsigned>(nb) * sizeof(cpx<T>));
-  for (int rest = threadIdx.x / H; rest < nrest_p; rest += rstep) {
-    const bool valid = rest < nrest;
-    const int rv = valid ? rest : 0;
-    const int bl = rv & bmask, k2 = rv >> bcl;
-    const int y = r + n1 * k2;
-    const int b = b0 + bl;
-    // fused real-space step: the potential at the x this lane writes, requested
-    // before the transform so that its latency hides behind it
-    T vp[E];
-    if constexpr (POT) {
-      const T* __restrict__ vrow =
-          reinterpret_cast<const T*>(a.pot) + static_cast<int64_t>(z * ny + y) * nx;
-#pragma unroll
-      for (int k = 0; k < E; ++k) vp[k] = vrow[k + E * q];
-    }
-    cpx<T> v[E];
-#pragma unroll
-    for (int j = 0; j < E; ++j)
-      v[j] = (valid && xs[j] >= 0) ? S[xs[j] * sx + (k2 << bcl) + bl] : cpx<T>{0, 0};
-    line_fft<E, H, +1, T, MF>(v, ctx);
-    if constexpr (POT) {
-      // the grid receives V(x, y, z) * psi
-#pragma unroll
-      for (int k = 0; k < E; ++k) v[k] = cscale(v[k], vp[k]);
-    }
-    if (valid && b < nb) {
-      if (a.plane32) {
-        // the plane as a buffer: one offset register per line, the x stride
-        // in a scalar register
-        const unsigned off =
-            static_cast<unsigned>((y * nx + E * q) * nb + b) * static_cast<unsigned>(sizeof(cpx<T>));
-#pragma unroll
-        for (int k = 0; k < E; ++k) buf_store(gplane, v[k], off, k * xstride);
-      } else {
-        cpx<T>* row = gout + static_cast<int64_t>(z * ny + y) * nx * nb + b;
-#pragma unroll
-        for (int k = 0; k < E; ++k) row[static_cast<int64_t>(k + E * q) * nb] = v[k];
-      }
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Forward x transform of the class rows y = r + n1*k2 (k2 < m) of plane z for
-// the bands b0 + bl, keeping the occupied x of slabs [x_lo, x_hi) as
-// S[xi - x_lo][k2][bl]. Lane h of a line keeps the same h for every row, so
-// its slab lookups are loaded once.
-template <typename T, int E, int H, bool MF>
-__device__ __forceinline__ void fwd_x_rows(const KArgs& a, const cpx<T>* __restrict__ gin,
-                                           const int32_t* __restrict__ xinv, cpx<T>* S, int r,
-                                           int z, int b0, int nb, int x_lo, int x_hi) {
-  constexpr int L = log2_const<H>();
-  const int bcl = a.bcl, bmask = (1 << bcl) - 1;
-  const int nx = a.nx, ny = a.ny, n1 = a.n1, sx = a.sx;
-  const cpx<T>* rootx = reinterpret_cast<const cpx<T>*>(a.rootx);
-  const cpx<T>* rootx_lo = reinterpret_cast<const cpx<T>*>(a.rootx_lo);
-  const int h = threadIdx.x % H;
-  const int q = bitrev_bits(h, L);
-  const auto ctx = line_ctx<E, H, -1, T>(h, rootx, rootx_lo);
-  int xs[E];
-#pragma unroll
-  for (int k = 0; k < E; ++k) {
-    const int xi = xinv[k + E * q] - x_lo;
-    xs[k] = (xi >= 0 && xi < x_hi - x_lo) ? xi : -1;
-  }
-  const int nrest = a.m << bcl;
-  const int per_wave = 64 / H;
-  const int nrest_p = MF ? (nrest + per_wave - 1) / per_wave * per_wave : nrest;
-  const int rstep = blockDim.x / H;
-  // plane z of the grid as a buffer (below 2 GiB when a.plane32 is set)
-  const __amdgpu_buffer_rsrc_t gplane = buf_rsrc(gin + static_cast<int64_t>(z) * ny * nx * nb);
-  const unsigned hstride =
-      __builtin_amdgcn_readfirstlane(static_cast<unsigned>(H * nb) * sizeof(cpx<T>));
-  for (int rest = threadIdx.x / H; rest < nrest_p; rest += rstep) {
-    const bool valid = rest < nrest;
-    const int rv = valid ? rest : 0;
-    const int bl = rv & bmask, k2 = rv >> bcl;
-    const int y = r + n1 * k2;
-    const int b = b0 + bl;
-    const bool ld = valid && b < nb;
-    cpx<T> v[E];
-    if (a.plane32) {
-      const unsigned off =
-          static_cast<unsigned>((y * nx + h) * nb + b) * static_cast<unsigned>(sizeof(cpx<T>));
-#pragma unroll
-      for (int j = 0; j < E; ++j)
-        v[j] = ld ? buf_load(gplane, gin, off, j * hstride) : cpx<T>{0, 0};
-    } else {
-      const cpx<T>* row = gin + static_cast<int64_t>(z * ny + y) * nx * nb + b;
-#pragma unroll
-      for (int j = 0; j < E; ++j)
-        v[j] = ld ? row[static_cast<int64_t>(h + H * j) * nb] : cpx<T>{0, 0};
-    }
-    line_fft<E, H, -1, T, MF>(v, ctx);
-    if (!valid) continue;
-#pragma unroll
-    for (int k = 0; k < E; ++k)
-      if (xs[k] >= 0) S[xs[k] * sx + (k2 << bcl) + bl] = v[k];
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Class-parallel forward task (plane z, chunk, class r): x transform of the
-// class rows, y transform of length m per (slab, band) line, then the class
-// partial Z_r[xi][j] = w_ny^{-j*r} * Y[xi][j] stored as Z[z][xi][j][r][band].
-template <typename T, int E, int H, bool MF>
-__device__ void k2r_fwd_cls_task(const KArgs& a, int t, cpx<T>* S) {
-  const int s = find_sphere_k2r(a, t);
-  const SphereDesc d = a.sph[s];
-  const int lt = t - d.k2_start;
-  const int n1 = a.n1, m = a.m;
-  const int r = lt % n1;
-  const int rest0 = lt / n1;
-  const int chunk = rest0 % d.nchunk, z = rest0 / d.nchunk;
-  const int bcl = a.bcl, bmask = (1 << bcl) - 1;
-  const int b0 = chunk << bcl;
-  const int ny = a.ny, sx = a.sx;
-  const int nb = d.nb, nslab = d.nslab;
-  const int32_t* __restrict__ xinv = a.xinv + d.xinv_off;
-  const cpx<T>* __restrict__ gin = reinterpret_cast<const cpx<T>*>(a.in) + d.grid_off;
-  const cpx<T>* twf = reinterpret_cast<const cpx<T>*>(a.twf);
-  const cpx<T>* twfl = reinterpret_cast<const cpx<T>*>(a.twf_lo);
-  const int nbp = d.nbp;
-  cpx<T>* __restrict__ zp = reinterpret_cast<cpx<T>*>(a.col) + d.zp_off +
-                            (static_cast<int64_t>(z) * nslab * ny + r) * nbp + b0;
-
-  fwd_x_rows<T, E, H, MF>(a, gin, xinv, S, r, z, b0, nb, 0, nslab);
-  __syncthreads();
-  const int nlines = nslab << bcl;
-  for (int it = threadIdx.x; it < nlines; it += blockDim.x) {
-    const int bl = it & bmask, xi = it >> bcl;
-    const cpx<T>* line = S + xi * sx + bl;
-    cpx<T> u[kMaxRadixDev];
-#pragma unroll
-    for (int j = 0; j < kMaxRadixDev; ++j)
-      if (j < m) u[j] = line[j << bcl];
-    butterfly<-1>(m, u);
-    cpx<T>* __restrict__ zl = zp + static_cast<int64_t>(xi) * ny * nbp + bl;
-#pragma unroll
-    for (int j = 0; j < kMaxRadixDev; ++j)
-      if (j < m) zl[j * n1 * nbp] = twmul<-1>(u[j], twf, twfl, j * r);
-  }
-}
-
-// ---------------------------------------------------------------------------
-template <typename T, int E, int H, bool MF>
-__device__ void k2r_fwd_task(const KArgs& a, int t, cpx<T>* S) {
-  const int s = find_sphere_k2r(a, t);
-  const SphereDesc d = a.sph[s];
-  const int lt = t - d.k2_start;
-  // task = (plane, chunk, split): split q owns the slabs [x_lo, x_hi) and their columns
-  const int q_split = lt % a.nsplit;
-  const int rest0 = lt / a.nsplit;
-  const int chunk = rest0 % d.nchunk, z = rest0 / d.nchunk;
-  const int x_lo = a.splits[d.split_off + q_split], x_hi = a.splits[d.split_off + q_split + 1];
-  const int bcl = a.bcl, bmask = (1 << bcl) - 1;
-  const int b0 = chunk << bcl;
-  const int ny = a.ny, n1 = a.n1, m = a.m, sx = a.sx;
-  const int nb = d.nb, npcol = d.npcol;
-  const int32_t* __restrict__ xinv = a.xinv + d.xinv_off;
-  const int32_t* __restrict__ cy = a.col_y + d.colmeta_off;
-  const int32_t* __restrict__ cxi = a.col_xi + d.colmeta_off;
-  const int32_t* __restrict__ cslot = a.col_slot + d.colmeta_off;
-  const int32_t* __restrict__ sst = a.slabstart + d.slab_off;
-  const int nbp = d.nbp;
-  cpx<T>* __restrict__ colp = reinterpret_cast<cpx<T>*>(a.col) + d.col_off +
-                              static_cast<int64_t>(z) * npcol * nbp + b0;
-  const cpx<T>* __restrict__ gin = reinterpret_cast<const cpx<T>*>(a.in) + d.grid_off;
-  const cpx<T>* twf = reinterpret_cast<const cpx<T>*>(a.twf);
-  const cpx<T>* twfl = reinterpret_cast<const cpx<T>*>(a.twf_lo);
-  cpx<T>* acc = S + a.lds_acc;
-  const bool acc_lds = a.acc_lds != 0;
-  const int c_lo = sst[x_lo];
-
-  for (int r = 0; r < n1; ++r) {
-    fwd_x_rows<T, E, H, MF>(a, gin, xinv, S, r, z, b0, nb, x_lo, x_hi);
-    __syncthreads();
-    // y-FFT of length m per occupied x of the split, in place
-    const int nlines = (x_hi - x_lo) << bcl;
-    for (int it = threadIdx.x; it < nlines; it += blockDim.x) {
-      const int bl = it & bmask, xl = it >> bcl;
-      cpx<T>* line = S + xl * sx + bl;
-      cpx<T> u[kMaxRadixDev];
-#pragma unroll
-      for (int j = 0; j < kMaxRadixDev; ++j)
-        if (j < m) u[j] = line[j << bcl];
-      butterfly<-1>(m, u);
-#pragma unroll
-      for (int j = 0; j < kMaxRadixDev; ++j)
-        if (j < m) line[j << bcl] = u[j];
-    }
-    __syncthreads();
-    // the class's contribution w_ny^{-y*r} * Y[xi][y mod m] to each column of the
-    // split, one (column, band) item per thread
-    const int c_hi = sst[x_hi];
-    const int nitems = (c_hi - c_lo) << bcl;
-    for (int it = threadIdx.x; it < nitems; it += blockDim.x) {
-      const int bl = it & bmask, cl = it >> bcl, c = c_lo + cl;
-      const int y = cy[c];
-      const cpx<T> val =
-          twmul<-1>(S[(cxi[c] - x_lo) * sx + ((y % m) << bcl) + bl], twf, twfl, (y * r) % ny);
-      cpx<T>* g = colp + static_cast<int64_t>(cslot[c]) * nbp + bl;
-      if (acc_lds) {
-        cpx<T>* p = acc + it;
-        if (n1 == 1) *g = val;
-        else if (r == 0) *p = val;
-        else if (r < n1 - 1) *p = cadd(*p, val);
-        else *g = cadd(*p, val);
-      } else {
-        *g = (r == 0) ? val : cadd(*g, val);
-      }
-    }
-    __syncthreads();
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Forward class combine (task = plane z, band chunk): column (xi, y = j + m*t)
-// = sum_r w_n1^{-t*r} Z_r[xi][j], the last, length-n1 stage of the
-// decimation-in-time split of the y transform. One (slab, j, band) item per
-// thread: its n1 class partials in, the n1 outputs t out to the columns that
-// exist.
-__device__ __forceinline__ int find_sphere_k3r(const KArgs& a, int t) {
-  int s = 0;
-  while (s + 1 < a.nsph && t >= a.sph[s].k3_end) ++s;
-  return s;
-}
-__device__ __forceinline__ bool codelet_radix(int R) {
-  return R == 1 || R == 2 || R == 3 || R == 4 || R == 5 || R == 6 || R == 8 || R == 9 ||
-         R == 10 || R == 12 || R == 15 || R == 16;
-}
-
-template <typename T>
-__device__ void k3r_task(const KArgs& a, int t) {
-  const int s = find_sphere_k3r(a, t);
-  const SphereDesc d = a.sph[s];
-  const int lt = t - d.k3_start;
-  const int chunk = lt % d.nchunk, z = lt / d.nchunk;
-  const int bcl = a.bcl, bmask = (1 << bcl) - 1;
-  const int b0 = chunk << bcl;
-  const int ny = a.ny, n1 = a.n1, m = a.m;
-  const int nslab = d.nslab, npcol = d.npcol;
-  const int nbp = d.nbp;
-  const cpx<T>* __restrict__ zp = reinterpret_cast<const cpx<T>*>(a.col) + d.zp_off +
-                                  static_cast<int64_t>(z) * nslab * ny * nbp + b0;
-  cpx<T>* __restrict__ colp = reinterpret_cast<cpx<T>*>(a.col) + d.col_off +
-                              static_cast<int64_t>(z) * npcol * nbp + b0;
-  const int32_t* __restrict__ cidx = a.colidx + d.colidx_off;
-  const cpx<T>* twf = reinterpret_cast<const cpx<T>*>(a.twf);
-  const cpx<T>* twfl = reinterpret_cast<const cpx<T>*>(a.twf_lo);
-  const float inv_m = 1.0f / static_cast<float>(m);
-  const int items = (nslab * m) << bcl;
-  if (codelet_radix(n1)) {
-    // NP items per thread per round (two in FP32); the partials and the column
-    // slots of all of them are requested before any of them is used
-    constexpr int NP = sizeof(T) == 4 ? 2 : 1;
-    // with a.plane32 the plane's partials and columns are addressed as buffers
-    constexpr unsigned es = sizeof(cpx<T>);
-    const unsigned nbp_es = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(nbp) * es);
-    const __amdgpu_buffer_rsrc_t rz = buf_rsrc(zp);
-    const __amdgpu_buffer_rsrc_t rc = buf_rsrc(colp);
-    for (int it0 = threadIdx.x; it0 < items; it0 += NP * blockDim.x) {
-      cpx<T> u[NP][kMaxRadixDev];
-      int cs[NP][kMaxRadixDev];
-      bool ok[NP];
-      int bls[NP];
-#pragma unroll
-      for (int p = 0; p < NP; ++p) {
-        const int it = it0 + p * blockDim.x;
-        ok[p] = it < items;
-        const int iv = ok[p] ? it : it0;
-        const int bl = iv & bmask;
-        const int jx = iv >> bcl;
-        const int xi = div_small(jx, m, inv_m);
-        const int j = jx - xi * m;
-        bls[p] = bl;
-        const int32_t* __restrict__ crow = cidx + xi * ny + j;
-        if (a.plane32) {
-          const unsigned off = static_cast<unsigned>((xi * ny + j * n1) * nbp + bl) * es;
-#pragma unroll
-          for (int r = 0; r < kMaxRadixDev; ++r) {
-            if (r < n1) {
-              u[p][r] = buf_load(rz, zp, off, r * nbp_es);
-              cs[p][r] = crow[r * m];
-            }
-          }
-        } else {
-          const cpx<T>* __restrict__ src = zp + (static_cast<int64_t>(xi) * ny + j * n1) * nbp + bl;
-#pragma unroll
-          for (int r = 0; r < kMaxRadixDev; ++r) {
-            if (r < n1) {
-              u[p][r] = src[r * nbp];
-              cs[p][r] = crow[r * m];
-            }
-          }
-        }
-      }
-#pragma unroll
-      for (int p = 0; p < NP; ++p) {
-        if (!ok[p]) continue;
-        butterfly<-1>(n1, u[p]);
-        if (a.plane32) {
-#pragma unroll
-          for (int q = 0; q < kMaxRadixDev; ++q)
-            if (q < n1 && cs[p][q] >= 0)
-              buf_store(rc, u[p][q], static_cast<unsigned>(cs[p][q] * nbp + bls[p]) * es, 0);
-        } else {
-#pragma unroll
-          for (int q = 0; q < kMaxRadixDev; ++q)
-            if (q < n1 && cs[p][q] >= 0) colp[static_cast<int64_t>(cs[p][q]) * nbp + bls[p]] = u[p][q];
-        }
-      }
-    }
-    return;
-  }
-  // class counts without a codelet: direct sums
-  for (int it = threadIdx.x; it < items; it += blockDim.x) {
-    const int bl = it & bmask;
-    const int jx = it >> bcl;
-    const int xi = div_small(jx, m, inv_m);
-    const int j = jx - xi * m;
-    const cpx<T>* __restrict__ src = zp + (static_cast<int64_t>(xi) * ny + j * n1) * nbp + bl;
-    const int32_t* __restrict__ crow = cidx + xi * ny + j;
-    for (int q = 0; q < n1; ++q) {
-      const int c = crow[q * m];
-      if (c < 0) continue;
-      cpx<T> acc = src[0];
-      const int step = m * q;  // w_n1^{q} = w_ny^{m*q}
-      int idx = 0;
-      for (int r = 1; r < n1; ++r) {
-        idx += step;
-        if (idx >= ny) idx -= ny;
-        acc = cadd(acc, twmul<-1>(src[r * nbp], twf, twfl, idx));
-      }
-      colp[static_cast<int64_t>(c) * nbp + bl] = acc;
-    }
-  }
-}
-
-template <typename T>
-__global__ void __launch_bounds__(256) k3r_kernel(const KArgs a) {
-  if (!a.persistent) {
-    const int t = static_task_g(a.k3_tasks, 1);
-    if (t >= 0) k3r_task<T>(a, t);
-    return;
-  }
-  __shared__ int sh_task;
-  for (;;) {
-    if (threadIdx.x == 0) sh_task = dynamic_task_g(a.counters + 16, a.k3_tasks, 1);
-    __syncthreads();
-    const int t = __builtin_amdgcn_readfirstlane(sh_task);
-    __syncthreads();
-    if (t < 0) break;
-    k3r_task<T>(a, t);
-  }
-}
+FFTB_REG_DECL_ALL(extern)
 
 hipError_t launch_combine(const KArgs& a, bool fp64, int grid, int threads, hipStream_t st) {
   if (fp64)
@@ -742,192 +15,62 @@ hipError_t launch_combine(const KArgs& a, bool fp64, int grid, int threads, hipS
   return hipGetLastError();
 }
 
-// ---------------------------------------------------------------------------
-template <int S, typename T, int E, int H, bool MF>
-__global__ void __launch_bounds__(256) k1r_kernel(const KArgs a) {
-  if (!a.persistent) {
-    const int t = static_task_g(a.k1_tasks, 1);
-    if (t >= 0) k1r_task<S, T, E, H, MF>(a, t);
-    return;
-  }
-  __shared__ int sh_task;
-  for (;;) {
-    if (threadIdx.x == 0) sh_task = dynamic_task_g(a.counters, a.k1_tasks, 1);
-    __syncthreads();
-    const int t = __builtin_amdgcn_readfirstlane(sh_task);
-    __syncthreads();
-    if (t < 0) break;
-    k1r_task<S, T, E, H, MF>(a, t);
-  }
-}
-
-// FC: forward tasks write class partials (compiled apart from the accumulating
-// forward so that neither variant's register allocation limits the other);
-// inverse tasks multiply by the real-space potential (compiled apart so that
-// the plain transform carries no potential registers)
-template <int S, typename T, int E, int H, bool MF, bool FC, int M>
-__global__ void __launch_bounds__(512) k2r_kernel(const KArgs a) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
-  if (!a.persistent) {
-    const int t = static_task_g(a.k2_tasks, a.g2);
-    if (t >= 0) {
-      if constexpr (S > 0) k2r_inv_task<T, E, H, MF, M, FC>(a, t, lds);
-      else if constexpr (FC) k2r_fwd_cls_task<T, E, H, MF>(a, t, lds);
-      else k2r_fwd_task<T, E, H, MF>(a, t, lds);
-    }
-    return;
-  }
-  __shared__ int sh_task;
-  for (;;) {
-    if (threadIdx.x == 0) sh_task = dynamic_task_g(a.counters + 8, a.k2_tasks, a.g2);
-    __syncthreads();
-    const int t = __builtin_amdgcn_readfirstlane(sh_task);
-    __syncthreads();
-    if (t < 0) break;
-    if constexpr (S > 0) k2r_inv_task<T, E, H, MF, M, FC>(a, t, lds);
-    else if constexpr (FC) k2r_fwd_cls_task<T, E, H, MF>(a, t, lds);
-    else k2r_fwd_task<T, E, H, MF>(a, t, lds);
-    __syncthreads();
-  }
-}
-
-// ---------------------------------------------------------------------------
-// (E, H) pairs compiled for each precision; the host picks one per axis.
-#define FFTB_REG_SHAPES_F64(X) \
-  X(4, 1) X(5, 1) X(6, 1) X(8, 1) X(9, 1) X(10, 1) X(12, 1) X(15, 1) X(16, 1) \
-  X(5, 4) X(6, 4) X(4, 8) X(12, 8) X(16, 8) X(18, 8) X(20, 8) X(45, 4)       \
-  X(6, 16) X(8, 16) X(9, 16) X(10, 16) X(16, 16)
-#define FFTB_REG_SHAPES_F32(X) \
-  X(4, 1) X(5, 1) X(6, 1) X(8, 1) X(9, 1) X(10, 1) X(12, 1) X(15, 1) X(16, 1) \
-  X(5, 4) X(6, 4) X(4, 8) X(12, 8) X(16, 8) X(18, 8) X(20, 8) X(45, 4)       \
-  X(6, 16) X(8, 16) X(9, 16) X(10, 16) X(16, 16)
-
 bool reg_shape_supported(bool fp64, int E, int H) {
-#define FFTB_CHK(e, h) if (E == e && H == h) return true;
-  if (fp64) {
-    FFTB_REG_SHAPES_F64(FFTB_CHK)
-  } else {
-    FFTB_REG_SHAPES_F32(FFTB_CHK)
-  }
+  (void)fp64;  // both precisions compile the same shapes
+#define FFTB_CHK(e, h, p) if (E == e && H == h) return true;
+  FFTB_REG_SHAPES(FFTB_CHK)
 #undef FFTB_CHK
   return false;
 }
 
-// Inverse plane kernels with a compile-time class length are compiled for the
-// lines spread over 8 or 16 lanes (x lengths 32 .. 160) and m = 8 or 16.
-constexpr bool fold_m_compiled(int H, int m) { return (H == 8 || H == 16) && (m == 8 || m == 16); }
-
-template <int S, typename T, int E, int H, bool MF, bool FC, int M>
-static hipError_t launch_k2(const KArgs& a, int grid, int threads, size_t lds, hipStream_t st) {
-  hipLaunchKernelGGL((k2r_kernel<S, T, E, H, MF, FC, M>), dim3(grid), dim3(threads), lds, st, a);
-  return hipGetLastError();
-}
-
-template <int S, typename T, int E, int H, bool MF, bool FC, int M>
-static hipError_t attr_k2(size_t lds) {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(k2r_kernel<S, T, E, H, MF, FC, M>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-}
-
-template <int S, typename T, int E, int H, bool MF>
-static hipError_t launch_one(int which, const KArgs& a, int grid, int threads, size_t lds,
-                             hipStream_t st, int fold_m) {
-  if (which == 1) {
-    hipLaunchKernelGGL((k1r_kernel<S, T, E, H, MF>), dim3(grid), dim3(threads), 0, st, a);
-    return hipGetLastError();
-  }
-  if constexpr (S < 0) {
-    if (a.fwd_cls) return launch_k2<S, T, E, H, MF, true, 0>(a, grid, threads, lds, st);
-  } else {
-    const bool pot = a.pot != nullptr;
-    if constexpr (fold_m_compiled(H, 8)) {
-      if (fold_m == 8)
-        return pot ? launch_k2<S, T, E, H, MF, true, 8>(a, grid, threads, lds, st)
-                   : launch_k2<S, T, E, H, MF, false, 8>(a, grid, threads, lds, st);
-      if (fold_m == 16)
-        return pot ? launch_k2<S, T, E, H, MF, true, 16>(a, grid, threads, lds, st)
-                   : launch_k2<S, T, E, H, MF, false, 16>(a, grid, threads, lds, st);
-    }
-    if (fold_m != 0) return hipErrorInvalidValue;
-    if (pot) return launch_k2<S, T, E, H, MF, true, 0>(a, grid, threads, lds, st);
-  }
-  if (fold_m != 0) return hipErrorInvalidValue;
-  return launch_k2<S, T, E, H, MF, false, 0>(a, grid, threads, lds, st);
-}
-
-template <int S, typename T, int E, int H, bool MF>
-static hipError_t attr_one(size_t lds) {
-  hipError_t e = attr_k2<S, T, E, H, MF, false, 0>(lds);
-  if (e == hipSuccess) e = attr_k2<S, T, E, H, MF, true, 0>(lds);
-  if constexpr (S > 0 && fold_m_compiled(H, 8)) {
-    if (e == hipSuccess) e = attr_k2<S, T, E, H, MF, false, 8>(lds);
-    if (e == hipSuccess) e = attr_k2<S, T, E, H, MF, false, 16>(lds);
-    if (e == hipSuccess) e = attr_k2<S, T, E, H, MF, true, 8>(lds);
-    if (e == hipSuccess) e = attr_k2<S, T, E, H, MF, true, 16>(lds);
-  }
-  return e;
-}
-
-// the FP32 DFT_16 on the matrix cores is compiled for lines of 16 values per lane
 bool mfma_shape_supported(bool fp64, int E, int H) { return !fp64 && E == 16 && H == 8; }
 
 bool fold_m_supported(int H, int m) { return fold_m_compiled(H, m); }
+
+namespace {
+template <int S, typename T>
+hipError_t dispatch_parts(int which, const KArgs& a, int E, int H, int grid, int threads,
+                          size_t lds, hipStream_t st, int fold_m, bool attr_only) {
+  bool found = false;
+  hipError_t e = reg_dispatch<S, T, 0>(which, a, E, H, grid, threads, lds, st, fold_m, attr_only, &found);
+  if (found) return e;
+  e = reg_dispatch<S, T, 1>(which, a, E, H, grid, threads, lds, st, fold_m, attr_only, &found);
+  if (found) return e;
+  e = reg_dispatch<S, T, 2>(which, a, E, H, grid, threads, lds, st, fold_m, attr_only, &found);
+  if (found) return e;
+  return hipErrorInvalidValue;
+}
+}  // namespace
 
 // which: 1 = column kernel (E, H of the z axis), 2 = plane kernel (E, H of x)
 hipError_t launch_reg(int which, const KArgs& a, bool inverse, bool fp64, int E, int H, int grid,
                       int threads, size_t lds, hipStream_t st, bool mfma, int fold_m) {
   if (mfma) {
     if (fp64 || E != 16 || H != 8) return hipErrorInvalidValue;
-    return inverse ? launch_one<+1, float, 16, 8, true>(which, a, grid, threads, lds, st, fold_m)
-                   : launch_one<-1, float, 16, 8, true>(which, a, grid, threads, lds, st, fold_m);
+    return inverse ? reg_dispatch_mfma<+1>(which, a, grid, threads, lds, st, fold_m, false)
+                   : reg_dispatch_mfma<-1>(which, a, grid, threads, lds, st, fold_m, false);
   }
-#define FFTB_L64(e, h)                                                                        \
-  if (E == e && H == h)                                                                       \
-    return inverse ? launch_one<+1, double, e, h, false>(which, a, grid, threads, lds, st,    \
-                                                         fold_m)                             \
-                   : launch_one<-1, double, e, h, false>(which, a, grid, threads, lds, st,    \
-                                                         fold_m);
-#define FFTB_L32(e, h)                                                                        \
-  if (E == e && H == h)                                                                       \
-    return inverse ? launch_one<+1, float, e, h, false>(which, a, grid, threads, lds, st,     \
-                                                        fold_m)                              \
-                   : launch_one<-1, float, e, h, false>(which, a, grid, threads, lds, st,     \
-                                                        fold_m);
-  if (fp64) {
-    FFTB_REG_SHAPES_F64(FFTB_L64)
-  } else {
-    FFTB_REG_SHAPES_F32(FFTB_L32)
-  }
-#undef FFTB_L64
-#undef FFTB_L32
-  return hipErrorInvalidValue;
+  if (fp64)
+    return inverse ? dispatch_parts<+1, double>(which, a, E, H, grid, threads, lds, st, fold_m, false)
+                   : dispatch_parts<-1, double>(which, a, E, H, grid, threads, lds, st, fold_m, false);
+  return inverse ? dispatch_parts<+1, float>(which, a, E, H, grid, threads, lds, st, fold_m, false)
+                 : dispatch_parts<-1, float>(which, a, E, H, grid, threads, lds, st, fold_m, false);
 }
 
 hipError_t prepare_reg(bool fp64, int E, int H, size_t lds, bool mfma) {
+  KArgs dummy{};
   if (mfma) {
     if (fp64 || E != 16 || H != 8) return hipErrorInvalidValue;
-    hipError_t err = attr_one<+1, float, 16, 8, true>(lds);
-    return err != hipSuccess ? err : attr_one<-1, float, 16, 8, true>(lds);
+    hipError_t err = reg_dispatch_mfma<+1>(2, dummy, 0, 0, lds, nullptr, 0, true);
+    return err != hipSuccess ? err : reg_dispatch_mfma<-1>(2, dummy, 0, 0, lds, nullptr, 0, true);
   }
-#define FFTB_A64(e, h)                                                      \
-  if (E == e && H == h) {                                                   \
-    hipError_t err = attr_one<+1, double, e, h, false>(lds);                \
-    return err != hipSuccess ? err : attr_one<-1, double, e, h, false>(lds); \
-  }
-#define FFTB_A32(e, h)                                                     \
-  if (E == e && H == h) {                                                  \
-    hipError_t err = attr_one<+1, float, e, h, false>(lds);                \
-    return err != hipSuccess ? err : attr_one<-1, float, e, h, false>(lds); \
-  }
+  hipError_t err;
   if (fp64) {
-    FFTB_REG_SHAPES_F64(FFTB_A64)
-  } else {
-    FFTB_REG_SHAPES_F32(FFTB_A32)
+    err = dispatch_parts<+1, double>(2, dummy, E, H, 0, 0, lds, nullptr, 0, true);
+    return err != hipSuccess ? err : dispatch_parts<-1, double>(2, dummy, E, H, 0, 0, lds, nullptr, 0, true);
   }
-#undef FFTB_A64
-#undef FFTB_A32
-  return hipErrorInvalidValue;
+  err = dispatch_parts<+1, float>(2, dummy, E, H, 0, 0, lds, nullptr, 0, true);
+  return err != hipSuccess ? err : dispatch_parts<-1, float>(2, dummy, E, H, 0, 0, lds, nullptr, 0, true);
 }
 
 }  // namespace fftb

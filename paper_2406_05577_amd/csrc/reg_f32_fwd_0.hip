@@ -1,0 +1,7 @@
+// Register-path kernels: F32 forward, shape part 0.
+#include "kernels_reg.hpp"
+
+namespace fftb {
+template hipError_t reg_dispatch<-1, float, 0>(int, const KArgs&, int, int, int, int, size_t,
+                                              hipStream_t, int, bool, bool*);
+}  // namespace fftb

@@ -1,0 +1,7 @@
+// Register-path kernels: F64 inverse, shape part 1.
+#include "kernels_reg.hpp"
+
+namespace fftb {
+template hipError_t reg_dispatch<+1, double, 1>(int, const KArgs&, int, int, int, int, size_t,
+                                              hipStream_t, int, bool, bool*);
+}  // namespace fftb
