@@ -41,6 +41,10 @@
  * Errors: every entry point returns an fftb_status. No C++ exception crosses
  * the ABI. fftb_last_error() gives a thread-local detail message for the last
  * failing call on the calling thread.
+ *
+ * Environment: FFTB_LOG (set, not "0") prints a plan summary on stderr at plan
+ * creation; FFTB_MAX_DEVICE_BYTES bounds the device memory of one plan (a plan
+ * that would exceed it fails with FFTB_ERR_NOMEM before any device call).
  */
 #ifndef FFTB_H
 #define FFTB_H
@@ -71,7 +75,11 @@ enum {
   FFTB_PLAN_BATCHED = 1,     /* persistent kernels walking a device work list over all spheres */
   FFTB_PLAN_AUTOTUNE = 2,    /* time candidate tilings at create time and keep the fastest per
                                 direction; results are cached in the file named by the
-                                FFTB_TUNE_CACHE environment variable (default: none) */
+                                FFTB_TUNE_CACHE environment variable (default: none). The
+                                trials share one scratch buffer, try at most
+                                FFTB_TUNE_MAX_CANDIDATES tilings per direction (default 16),
+                                stop after FFTB_TUNE_SECONDS (default 60) keeping the best so
+                                far, and print one progress line per trial on stderr */
   FFTB_PLAN_GRAPH = 4,       /* replay each direction as a captured hipGraph */
   FFTB_PLAN_HOST_ONLY = 8,   /* build and validate the host tables only; no device work (testing) */
   FFTB_PLAN_MFMA = 16        /* FFTB_C64 only: radix-16 stages as FP32 MFMA dense products */

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -47,6 +48,24 @@ thread_local std::string g_last_error;
 fftb_status fail(fftb_status s, const std::string& msg) {
   g_last_error = msg;
   return s;
+}
+
+// Column scratch shared by the autotuner's trial plans: set while the trials
+// run on this thread, so that each trial borrows it (growing it when a trial
+// needs more) instead of allocating and freeing its own.
+struct TuneScratch {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+thread_local TuneScratch* g_tune_scratch = nullptr;
+
+// Upper bound on the device memory one plan may hold (FFTB_MAX_DEVICE_BYTES,
+// bytes; unset or 0 = no bound). A plan that would exceed it fails with
+// FFTB_ERR_NOMEM before any device call.
+size_t device_byte_cap() {
+  const char* v = std::getenv("FFTB_MAX_DEVICE_BYTES");
+  if (!v || !*v) return 0;
+  return static_cast<size_t>(std::strtoull(v, nullptr, 10));
 }
 
 constexpr size_t kLdsMax = 160 * 1024 - 1024;  // leave room for static LDS
@@ -505,6 +524,8 @@ fftb_status choose_dir(fftb_plan_s& P, int d, const fftb_dir_tuning& t) {
   D.n1 = n1;
   D.m = m;
   D.lx = lx;
+  // the LDS-stage kernels are compiled for at most 256 threads per workgroup
+  D.threads = std::min(D.threads, 256);
   D.ay = aym;
   D.lds2 = bytes;
   D.lds_P = offP;
@@ -633,6 +654,9 @@ void build_descs(fftb_plan_s& P, DirCfg& D) {
 }
 
 fftb_status dev_alloc(fftb_plan_s& P, size_t bytes, void** out) {
+  const size_t cap = device_byte_cap();
+  if (cap && P.dev_bytes + bytes > cap)
+    return fail(FFTB_ERR_NOMEM, "plan would exceed FFTB_MAX_DEVICE_BYTES");
   void* p = nullptr;
   hipError_t e = hipMalloc(&p, std::max<size_t>(bytes, 256));
   if (e != hipSuccess) {
@@ -726,10 +750,29 @@ fftb_status device_setup(fftb_plan_s& P, hipStream_t st) {
   if ((s = upload_tw(P, root_table(P.nx), &P.d_rootx, &P.d_rootx_lo, st)) != FFTB_OK) return s;
   if ((s = upload_tw(P, root_table(P.nz), &P.d_rootz, &P.d_rootz_lo, st)) != FFTB_OK) return s;
   const int64_t col_elems = P.dir[0].col_elems + P.dir[1].col_elems;
-  if ((s = dev_alloc(P, static_cast<size_t>(col_elems) * es_of(P.dtype), &P.d_col)) != FFTB_OK)
+  const size_t col_bytes = static_cast<size_t>(col_elems) * es_of(P.dtype);
+  if (g_tune_scratch) {
+    // an autotuning trial: borrow the tuner's scratch (the previous trial has
+    // completed; the tuner synchronises after every trial)
+    TuneScratch& ts = *g_tune_scratch;
+    if (ts.bytes < col_bytes) {
+      if (ts.p) (void)hipFree(ts.p);
+      ts.p = nullptr;
+      ts.bytes = 0;
+      e = hipMalloc(&ts.p, std::max<size_t>(col_bytes, 256));
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(FFTB_ERR_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+      }
+      ts.bytes = col_bytes;
+    }
+    P.d_col = ts.p;
+  } else if ((s = dev_alloc(P, col_bytes, &P.d_col)) != FFTB_OK) {
     return s;
-  // padding slots of the column scratch must read as zero
-  e = hipMemsetAsync(P.d_col, 0, static_cast<size_t>(col_elems) * es_of(P.dtype), st);
+  }
+  // the padding slots of the inverse's column region must read as zero (no
+  // kernel writes them); every other scratch value is written before it is read
+  e = hipMemsetAsync(P.d_col, 0, static_cast<size_t>(P.dir[0].col_elems) * es_of(P.dtype), st);
   if (e != hipSuccess) return fail(FFTB_ERR_HIP, std::string("hipMemsetAsync: ") + hipGetErrorString(e));
   if ((s = dev_alloc(P, 24 * sizeof(unsigned int), &p)) != FFTB_OK) return s;
   P.d_counters = static_cast<unsigned int*>(p);
@@ -906,7 +949,7 @@ hipError_t enqueue(fftb_plan_s* P, const KArgs& a, const DirCfg& D, bool inverse
                      which == 1 ? 0 : D.lds2, st, which == 1 ? D.mf1 : D.mf2,
                      which == 1 ? 0 : D.fold_m);
     } else {
-      e = launch_kernel(which, a, inverse, fp64, which == 1 ? g1 : g2, D.threads,
+      e = launch_kernel(which, a, inverse, fp64, which == 1 ? g1 : g2, std::min(D.threads, 256),
                         which == 1 ? D.lds1 : D.lds2, st);
     }
     if (e != hipSuccess) return e;
@@ -964,6 +1007,32 @@ fftb_status run(fftb_plan_s* P, const void* in, void* out, void* stream, bool in
 // inside a graph capture) and keep the fastest per direction. Results are
 // cached per input (FNV-1a hash of dims, dtype, persistent flag, the spheres'
 // sizes and maps) in the file named by FFTB_TUNE_CACHE, if set.
+
+// Plan summary on stderr when FFTB_LOG is set (to anything but 0).
+void log_plan(const fftb_plan_s& P) {
+  const char* v = std::getenv("FFTB_LOG");
+  if (!v || !*v || std::strcmp(v, "0") == 0) return;
+  std::fprintf(stderr,
+               "fftb plan: grid %dx%dx%d, %zu sphere(s), %lld coefficients, %lld columns, %s, "
+               "flags %u, %s, device %.3f GB (scratch %.3f GB)\n",
+               P.nx, P.ny, P.nz, P.sph.size(), static_cast<long long>(P.total_coeffs),
+               static_cast<long long>(P.total_columns), P.dtype == FFTB_C128 ? "complex128" : "complex64",
+               P.flags, P.autotuned == 1 ? "autotuned" : P.autotuned == 2 ? "tuning from cache" : "default tiling",
+               P.dev_bytes / 1e9,
+               static_cast<double>(P.dir[0].col_elems + P.dir[1].col_elems) * es_of(P.dtype) / 1e9);
+  for (int d = 0; d < 2; ++d) {
+    const DirCfg& D = P.dir[d];
+    std::fprintf(stderr,
+                 "  %s: band chunk %d, %d y classes of %d, %d threads, column kernel %s (%dx%d, %d "
+                 "columns/task, %d tasks), plane kernel %s (%dx%d, LDS %zu B, %d tasks)%s%s, "
+                 "fold m %d\n",
+                 d == 0 ? "inverse" : "forward", D.bc, D.n1, D.m, D.threads,
+                 D.reg1 ? "register" : "LDS-stage", D.e1, D.h1, D.lc, D.k1_tasks,
+                 D.reg2 ? "register" : "LDS-stage", D.e2, D.h2, D.lds2, D.k2_tasks,
+                 D.fwd_cls ? ", class partials + combine" : "", D.mf2 || D.mf1 ? ", matrix-core DFT_16" : "",
+                 D.fold_m);
+  }
+}
 
 uint64_t plan_key(const int32_t dims[3], const fftb_sphere* spheres, int nsph, fftb_dtype dt,
                   uint32_t flags) {
@@ -1045,58 +1114,101 @@ void cache_store(uint64_t key, const fftb_tuning& t) {
   std::fclose(f);
 }
 
-// Candidate tilings of one direction around the library defaults.
-std::vector<fftb_dir_tuning> candidates(const fftb_plan_s& P, bool inverse, const fftb_dir_tuning& base) {
-  std::vector<fftb_dir_tuning> out;
+// Effective tiling of one direction as choose_dir resolves it (the fields
+// that tell two candidates apart).
+struct DirKey {
+  int v[9];
+  bool operator==(const DirKey& o) const { return std::memcmp(v, o.v, sizeof v) == 0; }
+};
+DirKey dir_key(const DirCfg& D, bool inverse) {
+  DirKey k = {{D.bc, D.n1, D.threads, (D.reg1 ? 1 : 0) | (D.reg2 ? 2 : 0), D.reg2 ? D.h2 : D.lx,
+               D.lc, inverse ? 0 : (D.fwd_cls ? 3 : D.acc_lds ? 1 : 2), D.nsplit, D.h1}};
+  return k;
+}
+
+// Candidate tilings of one direction around the library defaults, most
+// promising first: band chunk (default, half, and twice for the inverse),
+// class count (default, ny/16, ny/8), 256 or 512 threads, the 8-lane line
+// shapes, and for the forward the class-partial and the LDS-accumulator
+// variants. The LDS-stage kernels are tried only where an axis has no
+// register shape. Candidates that resolve to the same tiling, or that do not
+// fit, are dropped; at most `cap` remain.
+std::vector<fftb_dir_tuning> candidates(fftb_plan_s& P, bool inverse, const fftb_dir_tuning& base,
+                                        size_t cap) {
   const bool fp64 = P.dtype == FFTB_C128;
+  const int d = inverse ? 0 : 1;
+  const DirCfg saved = P.dir[d];
+  const std::string saved_err = g_last_error;
+  std::vector<fftb_dir_tuning> raw;
   const int bc0 = default_bc(P, fp64 ? 8 : 16);
   std::vector<int> bcs = {bc0};
   if (bc0 / 2 >= 1) bcs.push_back(bc0 / 2);
   if (inverse && bc0 * 2 <= default_bc(P, 64)) bcs.push_back(bc0 * 2);
   std::vector<int> classes = {0};
   for (int m : {16, 8})
-    if (P.ny % m == 0) classes.push_back(P.ny / m);
-  for (int bc : bcs) {
-    for (int n1 : classes) {
-      for (int threads : {256, 512}) {
-        if (inverse) {
+    if (P.ny % m == 0 && P.ny / m > 1) classes.push_back(P.ny / m);
+  raw.push_back(base);
+  for (int lanes : {0, 8}) {
+    for (int bc : bcs) {
+      for (int n1 : classes) {
+        for (int threads : {256, 512}) {
           fftb_dir_tuning t = base;
           t.band_chunk = bc;
           t.y_classes = n1;
           t.threads = threads;
           t.path = 0;
-          out.push_back(t);
-          if (bc == bc0) {
-            t.lanes = 8;  // the 8-lane line shapes against the default (most lanes)
-            out.push_back(t);
-          }
-        } else {
-          for (int acc : {3, 1, 2}) {
-            for (int extra : {0, 1}) {
-              if (acc != 1 && extra) continue;
-              fftb_dir_tuning t = base;
-              t.band_chunk = bc;
-              t.y_classes = n1;
-              t.threads = threads;
-              t.path = 0;
+          t.lanes = lanes;
+          if (inverse) {
+            raw.push_back(t);
+          } else {
+            for (int acc : {3, 1}) {
               t.acc = acc;
-              t.splits = extra ? -1 : 0;  // -1: one more split than the smallest that fits
-              out.push_back(t);
-              if (acc == 3 && bc == bc0) {
-                t.lanes = 8;
-                out.push_back(t);
-              }
+              raw.push_back(t);
             }
           }
         }
       }
     }
-    fftb_dir_tuning g = base;  // LDS-stage kernels
-    g.band_chunk = bc;
-    g.path = 1;
-    out.push_back(g);
   }
+  // the LDS-stage kernels, only where the default has no register path
+  bool reg_default = false;
+  if (choose_dir(P, d, base) == FFTB_OK) reg_default = P.dir[d].reg1 && P.dir[d].reg2;
+  if (!reg_default) {
+    for (int bc : bcs) {
+      fftb_dir_tuning g = base;
+      g.band_chunk = bc;
+      g.path = 1;
+      raw.push_back(g);
+    }
+  }
+  std::vector<fftb_dir_tuning> out;
+  std::vector<DirKey> seen;
+  for (const auto& t : raw) {
+    if (out.size() >= cap) break;
+    P.dir[d] = DirCfg();
+    if (choose_dir(P, d, t) != FFTB_OK) continue;
+    const DirKey k = dir_key(P.dir[d], inverse);
+    if (std::find(seen.begin(), seen.end(), k) != seen.end()) continue;
+    seen.push_back(k);
+    out.push_back(t);
+  }
+  P.dir[d] = saved;
+  g_last_error = saved_err;
   return out;
+}
+
+std::string tiling_str(const fftb_dir_tuning& t) {
+  char b[160];
+  std::snprintf(b, sizeof b, "bc=%d n1=%d thr=%d lanes=%d acc=%d path=%d", t.band_chunk,
+                t.y_classes, t.threads, t.lanes, t.acc, t.path);
+  return b;
+}
+
+double env_seconds(const char* name, double dflt) {
+  const char* v = std::getenv(name);
+  if (!v || !*v) return dflt;
+  const double x = std::atof(v);
+  return x > 0 ? x : dflt;
 }
 
 fftb_status autotune(fftb_plan_s& P, const int32_t dims[3], const fftb_sphere* spheres, int nsph,
@@ -1106,6 +1218,8 @@ fftb_status autotune(fftb_plan_s& P, const int32_t dims[3], const fftb_sphere* s
     P.autotuned = 2;
     return FFTB_OK;
   }
+  const size_t cap = static_cast<size_t>(env_seconds("FFTB_TUNE_MAX_CANDIDATES", 16));
+  const double budget = env_seconds("FFTB_TUNE_SECONDS", 60.0);
   const int es = es_of(dtype);
   void *sin = nullptr, *sout = nullptr, *grid = nullptr;
   if (hipMalloc(&sin, P.sphere_elems * es) != hipSuccess ||
@@ -1118,8 +1232,8 @@ fftb_status autotune(fftb_plan_s& P, const int32_t dims[3], const fftb_sphere* s
   }
   (void)hipMemsetAsync(sin, 0, P.sphere_elems * es, st);
   (void)hipMemsetAsync(grid, 0, P.grid_elems * es, st);
-  std::vector<fftb_dir_tuning> ci = candidates(P, true, t.inv);
-  std::vector<fftb_dir_tuning> cf = candidates(P, false, t.fwd);
+  const std::vector<fftb_dir_tuning> ci = candidates(P, true, t.inv, cap);
+  const std::vector<fftb_dir_tuning> cf = candidates(P, false, t.fwd, cap);
   const size_t n = std::max(ci.size(), cf.size());
   double best[2] = {1e30, 1e30};
   fftb_dir_tuning pick[2] = {t.inv, t.fwd};
@@ -1127,46 +1241,59 @@ fftb_status autotune(fftb_plan_s& P, const int32_t dims[3], const fftb_sphere* s
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
   const std::string saved_err = g_last_error;
-  for (size_t i = 0; i < n; ++i) {
+  TuneScratch scratch;
+  g_tune_scratch = &scratch;
+  const auto t_start = std::chrono::steady_clock::now();
+  std::fprintf(stderr, "fftb autotune: %zu inverse and %zu forward candidates, budget %.0f s\n",
+               ci.size(), cf.size(), budget);
+  size_t i = 0;
+  for (; i < n; ++i) {
+    const double el =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    if (el > budget) break;
     fftb_tuning c = t;
     c.inv = ci[std::min(i, ci.size() - 1)];
     c.fwd = cf[std::min(i, cf.size() - 1)];
-    int extra_split = 0;
-    if (c.fwd.splits < 0) {
-      c.fwd.splits = 0;
-      extra_split = 1;
-    }
     fftb_plan sub = nullptr;
     const uint32_t sflags = flags & ~(FFTB_PLAN_AUTOTUNE | FFTB_PLAN_GRAPH);
-    if (extra_split) {
-      // find the smallest split count, then ask for one more
-      fftb_plan probe = nullptr;
-      if (fftb_plan_create(&probe, dims, spheres, nsph, dtype, sflags | FFTB_PLAN_HOST_ONLY, &c,
-                           nullptr) != FFTB_OK)
-        continue;
-      c.fwd.splits = std::min(8, probe->dir[1].nsplit + 1);
-      fftb_plan_destroy(probe);
-    }
-    if (fftb_plan_create(&sub, dims, spheres, nsph, dtype, sflags, &c, st) != FFTB_OK) continue;
-    for (int d = 0; d < 2; ++d) {
-      const bool inv = d == 0;
-      const void* in = inv ? sin : grid;
-      void* out = inv ? grid : sout;
-      fftb_status ok = run(sub, in, out, st, inv);
-      if (ok == FFTB_OK && hipEventRecord(e0, st) == hipSuccess) {
-        for (int r = 0; r < 3 && ok == FFTB_OK; ++r) ok = run(sub, in, out, st, inv);
+    double ms_dir[2] = {-1, -1};
+    if (fftb_plan_create(&sub, dims, spheres, nsph, dtype, sflags, &c, st) == FFTB_OK) {
+      for (int d = 0; d < 2; ++d) {
+        const bool inv = d == 0;
+        if (i >= (inv ? ci.size() : cf.size())) continue;  // this direction's list is done
+        const void* in = inv ? sin : grid;
+        void* out = inv ? grid : sout;
+        // one warm-up; then 3 timed executions, or 1 when one takes over 50 ms
+        fftb_status ok = FFTB_OK;
         float ms = 0.f;
+        if (hipEventRecord(e0, st) != hipSuccess) ok = FFTB_ERR_HIP;
+        if (ok == FFTB_OK) ok = run(sub, in, out, st, inv);
+        if (ok == FFTB_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                              hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+          ok = FFTB_ERR_HIP;
+        const int reps = ms > 50.f ? 1 : 3;
+        if (ok == FFTB_OK && hipEventRecord(e0, st) != hipSuccess) ok = FFTB_ERR_HIP;
+        for (int r = 0; r < reps && ok == FFTB_OK; ++r) ok = run(sub, in, out, st, inv);
         if (ok == FFTB_OK && hipEventRecord(e1, st) == hipSuccess &&
-            hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess &&
-            ms < best[d]) {
-          best[d] = ms;
-          pick[d] = inv ? c.inv : c.fwd;
+            hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) {
+          ms_dir[d] = ms / reps;
+          if (ms_dir[d] < best[d]) {
+            best[d] = ms_dir[d];
+            pick[d] = inv ? c.inv : c.fwd;
+          }
         }
       }
+      fftb_plan_destroy(sub);
     }
-    fftb_plan_destroy(sub);
+    (void)hipStreamSynchronize(st);
+    std::fprintf(stderr, "fftb autotune %zu/%zu: inv [%s] %.3f ms | fwd [%s] %.3f ms\n", i + 1, n,
+                 i < ci.size() ? tiling_str(c.inv).c_str() : "-", ms_dir[0],
+                 i < cf.size() ? tiling_str(c.fwd).c_str() : "-", ms_dir[1]);
+    std::fflush(stderr);
   }
+  g_tune_scratch = nullptr;
   (void)hipStreamSynchronize(st);
+  if (scratch.p) (void)hipFree(scratch.p);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   (void)hipFree(sin);
@@ -1176,6 +1303,9 @@ fftb_status autotune(fftb_plan_s& P, const int32_t dims[3], const fftb_sphere* s
   g_last_error = saved_err;
   if (best[0] < 1e30) t.inv = pick[0];
   if (best[1] < 1e30) t.fwd = pick[1];
+  std::fprintf(stderr, "fftb autotune: %zu of %zu trials in %.1f s; inverse [%s] %.3f ms, forward [%s] %.3f ms\n",
+               i, n, std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count(),
+               tiling_str(t.inv).c_str(), best[0], tiling_str(t.fwd).c_str(), best[1]);
   P.autotuned = 1;
   cache_store(key, t);
   return FFTB_OK;
@@ -1263,9 +1393,16 @@ fftb_status fftb_plan_create(fftb_plan* out, const int32_t dims[3], const fftb_s
       o.lanes = D.reg2 ? D.h2 : (D.reg1 ? D.h1 : 0);
     }
     if (!(flags & FFTB_PLAN_HOST_ONLY)) {
+      const size_t cap = device_byte_cap();
+      const size_t scratch = static_cast<size_t>(P->dir[0].col_elems + P->dir[1].col_elems) *
+                             es_of(dtype);
+      if (cap && !g_tune_scratch && scratch > cap)
+        return fail(FFTB_ERR_NOMEM, "plan scratch of " + std::to_string(scratch) +
+                                        " bytes exceeds FFTB_MAX_DEVICE_BYTES");
       fftb_status st = device_setup(*P, static_cast<hipStream_t>(stream));
       if (st != FFTB_OK) return st;
     }
+    if (!g_tune_scratch) log_plan(*P);
     *out = P.release();
     return FFTB_OK;
   } catch (const std::bad_alloc&) {

@@ -197,3 +197,57 @@ def test_cuboid_plan_tables():
     _expect_status(pk.FFTB_ERR_INVALID, lambda: pk.Plan.cuboid((12, 0, 6), 3, flags=pk.PLAN_HOST_ONLY))
     _expect_status(pk.FFTB_ERR_INVALID, lambda: pk.Plan.cuboid(dims, 0, flags=pk.PLAN_HOST_ONLY))
     _expect_status(pk.FFTB_ERR_UNSUPPORTED, lambda: pk.Plan.cuboid((14, 10, 6), 3, flags=pk.PLAN_HOST_ONLY))
+
+
+def test_generic_path_threads_clamped():
+    """The LDS-stage kernels are compiled for at most 256 threads: a 512-thread
+    request on a grid without register shapes (64^3) is clamped at plan time."""
+    m, lin = synth.sphere_map((64, 64, 64), (16, 16, 16))
+    p = host_plan((64, 64, 64), [lin], nb=8, tuning=dict(threads=512))
+    for d in ("inv", "fwd"):
+        t = p.info["tuning"][d]
+        assert t["path"] == 1 and t["threads"] == 256, t
+
+
+def test_device_byte_cap_gives_nomem(monkeypatch):
+    """FFTB_MAX_DEVICE_BYTES bounds a plan's device memory; a plan whose
+    scratch would exceed it fails with FFTB_ERR_NOMEM before any device call
+    (so this runs on a machine without a GPU)."""
+    monkeypatch.setenv("FFTB_MAX_DEVICE_BYTES", "4096")
+    m, lin = synth.sphere_map((32, 32, 32), (8, 8, 8))
+    with pytest.raises(fb.FftbError) as ex:
+        pk.Plan((32, 32, 32), [lin], 4, flags=0, stream=0)
+    assert ex.value.status == pk.FFTB_ERR_NOMEM
+    assert b"FFTB_MAX_DEVICE_BYTES" in pk.lib().fftb_last_error()
+
+
+def test_plan_log(monkeypatch, capfd):
+    """FFTB_LOG prints a plan summary (dims, tiling of both directions) on stderr."""
+    monkeypatch.setenv("FFTB_LOG", "1")
+    m, lin = synth.sphere_map((32, 32, 32), (8, 8, 8))
+    host_plan((32, 32, 32), [lin], nb=4)
+    err = capfd.readouterr().err
+    assert "fftb plan: grid 32x32x32" in err
+    assert "inverse: band chunk" in err and "forward: band chunk" in err
+    monkeypatch.setenv("FFTB_LOG", "0")
+    host_plan((32, 32, 32), [lin], nb=4)
+    assert "fftb plan" not in capfd.readouterr().err
+
+
+def test_plan_tables_under_sanitizers(tmp_path):
+    """plan.cpp (the host table builder) compiled with g++ and the address and
+    undefined-behaviour sanitizers, run on spheres, ellipsoids, permuted and
+    malformed maps, and every 2,3,5-smooth axis length up to 400."""
+    import shutil
+    import subprocess
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not available")
+    exe = tmp_path / "plan_check"
+    src = os.path.join(ROOT, "tests", "native", "plan_check.cpp")
+    plan = os.path.join(ROOT, "paper_2406_05577_amd", "csrc", "plan.cpp")
+    subprocess.run([gxx, "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined",
+                    "-fno-sanitize-recover=undefined", src, plan, "-o", str(exe)], check=True)
+    res = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    assert res.returncode == 0, res.stderr
+    assert "plan_check OK" in res.stdout
