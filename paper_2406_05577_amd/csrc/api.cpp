@@ -1250,7 +1250,7 @@ fftb_status autotune(fftb_plan_s& P, const int32_t dims[3], const fftb_sphere* s
   for (; i < n; ++i) {
     const double el =
         std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
-    if (el > budget) break;
+    if (i > 0 && el > budget) break;  // the first trial always runs
     fftb_tuning c = t;
     c.inv = ci[std::min(i, ci.size() - 1)];
     c.fwd = cf[std::min(i, cf.size() - 1)];

@@ -44,8 +44,8 @@ REG_CASES = [
     ((144, 160, 180), (36, 40, 45), [(0.12, -0.3, 0.27)], 2, 14),
 ]
 REG_TUNINGS = [None, dict(fwd_acc=2), dict(fwd_acc=1, fwd_band_chunk=2, fwd_splits=3),
-               dict(y_classes=4, fwd_y_classes=8), dict(band_chunk=2, col_tile=3, fwd_band_chunk=4),
-               dict(fwd_splits=5, threads=512), dict(fwd_acc=3, y_classes=8, threads=512),
+               dict(y_classes=16, fwd_y_classes=16), dict(band_chunk=2, col_tile=3, fwd_band_chunk=4),
+               dict(fwd_splits=5, threads=512), dict(fwd_acc=3, y_classes=16, threads=512),
                dict(fwd_acc=3, fwd_band_chunk=2, fwd_col_tile=5)]
 
 
@@ -100,11 +100,20 @@ def test_batched_and_graph(which, flags, dtype):
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-def test_forward_not_band_limited(dtype):
-    dims, semi, kpts, nb, seed = CASES[4]
+@pytest.mark.parametrize("case", ["small"] + [f"reg{i}" for i in range(4)])
+def test_forward_not_band_limited(case, dtype):
+    """The forward of a dense random grid (not band-limited) is the exact
+    gather of its full 3D DFT: a small mixed-radix grid, and the register
+    line shapes of the benchmark grids (32^3, 96^3, 128^3, 144x160x180)."""
+    if case == "small":
+        dims, semi, kpts, nb, seed = CASES[4]
+    else:
+        dims, semi, kpts, nb, seed = REG_CASES[int(case[3:])]
+        kpts = kpts[:1]
     w = synth.small_workload(dims, semi, kpts, nb, seed=seed)
     g = [synth.random_grid(np.random.default_rng(99), dims, nb)]
     e = check_workload(w, dtype, grid_in=g)
+    print(case, dtype, e)
     assert e[1] <= TOL[dtype], e
 
 
@@ -287,6 +296,25 @@ def test_autotune_and_cache(tmp_path, monkeypatch):
         e = check_workload(w, dtype, flags=2)
         assert max(e) <= TOL[dtype], e
     assert (tmp_path / "tune.txt").read_text().count("fftb-tune-v2") == 2
+
+
+def test_autotune_budget(tmp_path, monkeypatch, capfd):
+    """A tiny time budget stops the autotuner after its first trial; the plan
+    keeps the best tiling found so far and stays correct; every trial prints
+    a progress line."""
+    from gpu_util import make_plan
+    monkeypatch.setenv("FFTB_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    monkeypatch.setenv("FFTB_TUNE_SECONDS", "0.000001")
+    dims, semi, kpts, nb, seed = REG_CASES[1]
+    w = synth.small_workload(dims, semi, kpts, nb, seed=seed)
+    p = make_plan(w, dtype="c64", flags=2)
+    assert p.info["autotuned"] == 1
+    p.close()
+    err = capfd.readouterr().err
+    assert err.count("fftb autotune 1/") == 1 and "fftb autotune 2/" not in err
+    assert "1 of" in err
+    e = check_workload(w, "c64", flags=2)
+    assert max(e) <= TOL["c64"], e
 
 
 @pytest.mark.parametrize("flags", [16, 16 | 1 | 4])
