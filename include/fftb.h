@@ -196,6 +196,25 @@ fftb_status fftb_grid_to_sphere(fftb_plan plan, const void* grid_in, void* spher
 fftb_status fftb_apply_potential(fftb_plan plan, const void* sphere_in, const void* potential,
                                  void* grid_work, void* sphere_out, void* stream);
 
+/* Bytes of the static device scratch that fftb_sphere_to_grid_static uses. */
+#define FFTB_STATIC_SCRATCH_BYTES (64u << 20)
+
+/* For callers that cannot allocate device memory when they transform (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): fftb_sphere_to_grid with the plan's column scratch replaced by
+ * a static device array of FFTB_STATIC_SCRATCH_BYTES (64 MiB) that the library
+ * holds on every GPU it runs on until the process ends. The call allocates
+ * nothing (no hipMalloc, no events, no graph instantiation, even for plans
+ * created with FFTB_PLAN_GRAPH: it enqueues the kernels directly). Arguments,
+ * layouts and results as for fftb_sphere_to_grid. Returns FFTB_ERR_UNSUPPORTED,
+ * without enqueuing anything, when the plan's inverse column scratch (its
+ * column slots x nz x band stride x value size) exceeds the static array.
+ * Every call on one GPU shares that GPU's array: the call clears the part it
+ * needs zero before its kernels run, and calls that overlap in time on one GPU
+ * (on different streams, or from different threads) race on the array. */
+fftb_status fftb_sphere_to_grid_static(fftb_plan plan, const void* sphere_in, void* grid_out,
+                                       void* stream);
+
 /* Fill *info. Valid for host-only plans too. */
 fftb_status fftb_plan_get_info(fftb_plan plan, fftb_plan_info* info);
 

@@ -34,6 +34,8 @@ hipError_t prepare_reg(bool fp64, int E, int H, size_t lds, bool mfma);
 bool mfma_shape_supported(bool fp64, int E, int H);
 bool fold_m_supported(int H, int m);
 hipError_t launch_combine(const KArgs& a, bool fp64, int grid, int threads, hipStream_t st);
+hipError_t static_scratch_ptr(void** out);
+hipError_t launch_zero_scratch(void* p, size_t bytes, hipStream_t st);
 }  // namespace fftb
 
 using namespace fftb;
@@ -1423,6 +1425,40 @@ fftb_status fftb_sphere_to_grid(fftb_plan plan, const void* sphere_in, void* gri
 fftb_status fftb_grid_to_sphere(fftb_plan plan, const void* grid_in, void* sphere_out, void* stream) {
   try {
     return run(plan, grid_in, sphere_out, stream, false);
+  } catch (...) {
+    return fail(FFTB_ERR_INVALID, "unexpected exception");
+  }
+}
+
+fftb_status fftb_sphere_to_grid_static(fftb_plan P, const void* sphere_in, void* grid_out,
+                                       void* stream) {
+  try {
+    if (!P) return fail(FFTB_ERR_INVALID, "null plan");
+    if (!P->device) return fail(FFTB_ERR_INVALID, "plan was created host-only");
+    if (!sphere_in || !grid_out) return fail(FFTB_ERR_INVALID, "null data pointer");
+    const DirCfg& D = P->dir[0];
+    const size_t need = static_cast<size_t>(D.col_elems) * es_of(P->dtype);
+    if (need > FFTB_STATIC_SCRATCH_BYTES)
+      return fail(FFTB_ERR_UNSUPPORTED,
+                  "the plan's inverse column scratch (" + std::to_string(need) +
+                      " bytes) exceeds the static scratch (" +
+                      std::to_string(static_cast<size_t>(FFTB_STATIC_SCRATCH_BYTES)) + " bytes)");
+    void* scr = nullptr;
+    hipError_t e = static_scratch_ptr(&scr);
+    if (e != hipSuccess)
+      return fail(FFTB_ERR_HIP, std::string("hipGetSymbolAddress: ") + hipGetErrorString(e));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    // the padding slots the inverse fold reads must be zero; the array keeps
+    // the previous call's contents (col_elems * value size is a multiple of 16)
+    e = launch_zero_scratch(scr, (need + 15) & ~size_t{15}, st);
+    if (e != hipSuccess) return fail(FFTB_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+    int g1, g2, g3;
+    grids(*P, D, g1, g2, g3);
+    KArgs a = make_args(*P, D, sphere_in, grid_out, true, nullptr);
+    a.col = scr;
+    e = enqueue(P, a, D, true, g1, g2, g3, st, false);
+    if (e != hipSuccess) return fail(FFTB_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+    return FFTB_OK;
   } catch (...) {
     return fail(FFTB_ERR_INVALID, "unexpected exception");
   }

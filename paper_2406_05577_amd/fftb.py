@@ -37,7 +37,7 @@ EXPORTS = [
     "fftb_plan_workspace_size", "fftb_plan_sphere_stats", "fftb_plan_sphere_columns",
     "fftb_plan_destroy", "fftb_status_string", "fftb_last_error",
     "fftb_plan_set_profiling", "fftb_plan_get_profile", "fftb_apply_potential",
-    "fftb_plan_create_cuboid",
+    "fftb_plan_create_cuboid", "fftb_sphere_to_grid_static",
 ]
 
 
@@ -123,6 +123,8 @@ def lib() -> C.CDLL:
     L.fftb_sphere_to_grid.restype = C.c_int
     L.fftb_grid_to_sphere.argtypes = [vp, vp, vp, vp]
     L.fftb_grid_to_sphere.restype = C.c_int
+    L.fftb_sphere_to_grid_static.argtypes = [vp, vp, vp, vp]
+    L.fftb_sphere_to_grid_static.restype = C.c_int
     L.fftb_apply_potential.argtypes = [vp, vp, vp, vp, vp, vp]
     L.fftb_apply_potential.restype = C.c_int
     L.fftb_plan_create_cuboid.argtypes = [C.POINTER(vp), C.POINTER(C.c_int32), C.c_int32, C.c_int,
@@ -296,6 +298,16 @@ class Plan:
         self._check_tensor(grid, self.info["grid_elems"], "grid")
         _check(lib().fftb_sphere_to_grid(self._h, sphere.data_ptr(), grid.data_ptr(),
                                          _stream_ptr(stream)))
+        return grid
+
+    def sphere_to_grid_static(self, sphere, grid, stream=None):
+        """sphere_to_grid with the library's static device scratch instead of
+        the plan's (fftb_sphere_to_grid_static): allocates nothing, so `grid`
+        must be given."""
+        self._check_tensor(sphere, self.info["sphere_elems"], "sphere")
+        self._check_tensor(grid, self.info["grid_elems"], "grid")
+        _check(lib().fftb_sphere_to_grid_static(self._h, sphere.data_ptr(), grid.data_ptr(),
+                                                _stream_ptr(stream)))
         return grid
 
     def grid_to_sphere(self, grid, sphere=None, stream=None):
