@@ -41,6 +41,7 @@ WORKLOADS = {
     "c4_fp64": ("c4", "c128", 0),
     "c4": ("c4", "c64", 1 | 4),
     "c2": ("c2", "c128", 0),
+    "c2_c64": ("c2", "c64", 0),
     "c3": ("c3", "c64", 0),
     "c1": ("c1", "c128", 0),
     "c3alt": ("c3alt", "c64", 0),
@@ -52,11 +53,12 @@ WORKLOADS = {
     "c3_full": ("c3", "c64", 0),
 }
 # the second (complex64 batched) form timed on the same inputs
-PAIRED = {"c5_fp64": "c5", "c4_fp64": "c4", "c2": "c3"}
+PAIRED = {"c5_fp64": "c5", "c4_fp64": "c4", "c2": "c2_c64"}
 DESCR = {
     "c1": "sphere<->grid 32^3, |G|<=8 (2109 coeffs), Gamma, 4 bands",
     "c2": "sphere<->grid 128^3, |G|<=32 (137065 coeffs), Gamma, 256 bands",
     "c3": "sphere<->grid 128^3, |G|<=32 (137065 coeffs), Gamma, 256 bands",
+    "c2_c64": "sphere<->grid 128^3, |G|<=32 (137065 coeffs), Gamma, 256 bands (the c2 inputs in complex64)",
     "c3alt": "sphere<->grid 32^3, |G|<=8 (2109 coeffs), Gamma, 256 bands",
     "c4": "sphere<->grid 96^3, 8 k-points, |G+k|<=24, 64 bands each (512 bands)",
     "c5": "sphere<->grid 144x160x180, ellipsoid (36,40,45), 4 k-points, 128 bands each (512 bands)",

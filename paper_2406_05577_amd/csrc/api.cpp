@@ -190,9 +190,13 @@ bool single_codelet(int m) {
 }
 
 // Register shape (E values per lane, H lanes per line) for a line of length n:
-// the most lanes with a compiled shape, or exactly `lanes` if given.
-bool reg_shape(int n, bool fp64, int& E, int& H, int lanes = 0) {
-  for (int h = 16; h >= 1; h >>= 1) {
+// the most lanes with a compiled shape, or exactly `lanes` if given. Lines of
+// 12 lanes (a radix-3 step across lane groups) serve the column kernel only and
+// only on request (allow12 = the lanes knob asks for 12): their bands are spread
+// over four waves, which measured slower than 4-lane lines at 180 points.
+bool reg_shape(int n, bool fp64, int& E, int& H, int lanes = 0, bool allow12 = false) {
+  for (int h : {16, 12, 8, 4, 2, 1}) {
+    if (h == 12 && !(allow12 && lanes == 12)) continue;
     if (lanes && h != lanes) continue;
     if (n % h) continue;
     if (reg_shape_supported(fp64, n / h, h)) {
@@ -316,15 +320,17 @@ fftb_status choose_dir(fftb_plan_s& P, int d, const fftb_dir_tuning& t) {
   D.threads = threads;
   // ---- column kernel
   int e1 = 0, h1 = 0;
-  if (t.lanes != 0 && t.lanes != 1 && t.lanes != 4 && t.lanes != 8 && t.lanes != 16)
-    return fail(FFTB_ERR_INVALID, "lanes must be 0, 1, 4, 8 or 16");
+  if (t.lanes != 0 && t.lanes != 1 && t.lanes != 4 && t.lanes != 8 && t.lanes != 12 &&
+      t.lanes != 16)
+    return fail(FFTB_ERR_INVALID, "lanes must be 0, 1, 4, 8, 12 or 16");
   // the matrix-core DFT_16 runs on lines of 16 values per lane over 8 lanes
   const int lanes = t.lanes ? t.lanes : ((P.flags & FFTB_PLAN_MFMA) && !fp64 ? 8 : 0);
-  D.reg1 = t.path != 1 && (reg_shape(P.nz, fp64, e1, h1, lanes) || reg_shape(P.nz, fp64, e1, h1));
+  D.reg1 = t.path != 1 && (reg_shape(P.nz, fp64, e1, h1, lanes, true) ||
+                           reg_shape(P.nz, fp64, e1, h1, 0, true));
   D.e1 = e1;
   D.h1 = h1;
   if (D.reg1) {
-    D.lc = t.col_tile ? t.col_tile : std::max(1, 512 / (bc * h1));
+    D.lc = t.col_tile ? t.col_tile : std::max(1, 512 / (bc * (h1 == 12 ? 16 : h1)));
     D.lds1 = 0;
   } else {
     const int nbz = nbuf_of(P.az.nst);
@@ -466,7 +472,7 @@ fftb_status choose_dir(fftb_plan_s& P, int d, const fftb_dir_tuning& t) {
       std::vector<int> rad;
       plan_radices(D.m, rad);
       make_axis_plan(D.m, rad, D.ay);
-      if (D.reg1 && !t.col_tile) D.lc = std::max(1, 512 / (bc * h1));
+      if (D.reg1 && !t.col_tile) D.lc = std::max(1, 512 / (bc * (h1 == 12 ? 16 : h1)));
     } else if (t.path == 2) {
       return fail(FFTB_ERR_UNSUPPORTED, "no register-path class split fits in LDS");
     }

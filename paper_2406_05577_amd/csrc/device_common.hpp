@@ -372,6 +372,43 @@ constexpr int log2_const() {
   return l;
 }
 
+// Lanes a transform line of H lanes occupies: a line of 12 lanes takes a row
+// of 16 (the unit of the cross-lane moves), whose last 4 lanes idle.
+template <int H>
+constexpr int lane_group() {
+  return H == 12 ? 16 : H;
+}
+
+// After line_fft, lane h holds the E outputs X[k + E*out_block(h)], k < E.
+template <int H>
+__device__ __forceinline__ int out_block(int h) {
+  if constexpr (H == 12) {
+    // radix-3 output c = h / 4, then the 4-point output bitrev2(h mod 4)
+    return (h >> 2) + 3 * (((h & 1) << 1) | ((h >> 1) & 1));
+  } else {
+    return bitrev_bits(h, log2_const<H>());
+  }
+}
+
+// exp(S*2*pi*i*j/12), j < 12 (the radix-3 step of 12-lane lines).
+template <int S, typename T>
+__device__ __forceinline__ cpx<T> root12(int j) {
+  const T c[12] = {static_cast<T>(kcos(0, 12)), static_cast<T>(kcos(1, 12)),
+                   static_cast<T>(kcos(2, 12)), static_cast<T>(kcos(3, 12)),
+                   static_cast<T>(kcos(4, 12)), static_cast<T>(kcos(5, 12)),
+                   static_cast<T>(kcos(6, 12)), static_cast<T>(kcos(7, 12)),
+                   static_cast<T>(kcos(8, 12)), static_cast<T>(kcos(9, 12)),
+                   static_cast<T>(kcos(10, 12)), static_cast<T>(kcos(11, 12))};
+  const T sn[12] = {static_cast<T>(ksin(0, 12)), static_cast<T>(ksin(1, 12)),
+                    static_cast<T>(ksin(2, 12)), static_cast<T>(ksin(3, 12)),
+                    static_cast<T>(ksin(4, 12)), static_cast<T>(ksin(5, 12)),
+                    static_cast<T>(ksin(6, 12)), static_cast<T>(ksin(7, 12)),
+                    static_cast<T>(ksin(8, 12)), static_cast<T>(ksin(9, 12)),
+                    static_cast<T>(ksin(10, 12)), static_cast<T>(ksin(11, 12))};
+  const int jj = ((j % 12) + 12) % 12;
+  return {c[jj], static_cast<T>(S) * sn[jj]};
+}
+
 // exp(S*2*pi*i*j/16), j < 16 (the roots needed by the cross-lane radix-2
 // rounds for groups of up to 16 lanes).
 template <int S, typename T>
@@ -482,8 +519,9 @@ __device__ __forceinline__ double dpp_xor(double x) {
 // keep the sum).
 template <int E, int H, int S, typename T>
 struct LineCtx {
-  static constexpr bool kHoist = E <= 10;
-  static constexpr int kRounds = H > 1 ? log2_const<H>() : 1;
+  static constexpr bool kHoist = E <= 10 || H == 12;
+  // radix-2 rounds across the lanes (for 12 lanes: those of the 4-lane part)
+  static constexpr int kRounds = H == 12 ? 2 : (H > 1 ? log2_const<H>() : 1);
   int h;
   const cpx<T>* rootN;
   const cpx<T>* rootN_lo;
@@ -491,12 +529,21 @@ struct LineCtx {
   cpx<T> twl[kHoist && std::is_same<T, float>::value ? E : 1];
   T sgn[kRounds];
   cpx<T> rw[kRounds];
+  // 12 lanes: the radix-3 step across the three 4-lane groups (byte
+  // addresses of the two partner lanes and the weights of the lane's own value
+  // and of the partners' values, the step's twiddle folded in)
+  int src1, src2;
+  cpx<T> a3[H == 12 ? 3 : 1];
 };
 
 template <int E, int H, int S, typename T>
 __device__ __forceinline__ LineCtx<E, H, S, T> line_ctx(int h, const cpx<T>* __restrict__ rootN,
                                                         const cpx<T>* __restrict__ rootN_lo) {
   LineCtx<E, H, S, T> c;
+  if constexpr (H == 12) {
+    // idle lanes (12..15 of the row) compute with the position of lane 0
+    if (h >= 12) h = 0;
+  }
   c.h = h;
   c.rootN = rootN;
   c.rootN_lo = rootN_lo;
@@ -513,7 +560,28 @@ __device__ __forceinline__ LineCtx<E, H, S, T> line_ctx(int h, const cpx<T>* __r
       }
     }
   }
-  if constexpr (H > 1) {
+  if constexpr (H == 12) {
+    // lane h = h0 + 4g: DFT_3 over g, output c = g, then the twiddle
+    // w_12^{h0*g}: Y = sum_g' x[g'] w_3^{g'*g} w_12^{h0*g}, with
+    // w_3^e = w_12^{4e}; partners g+1 and g+2 (mod 3) of the same h0
+    const int h0 = h & 3, g = h >> 2;
+    const int g1 = g == 2 ? 0 : g + 1, g2 = g == 0 ? 2 : g - 1;
+    const int row = (threadIdx.x & 63) & ~15;
+    c.src1 = (row + h0 + 4 * g1) << 2;
+    c.src2 = (row + h0 + 4 * g2) << 2;
+    c.a3[0] = root12<S, T>(4 * g * g + h0 * g);
+    c.a3[1] = root12<S, T>(4 * g1 * g + h0 * g);
+    c.a3[2] = root12<S, T>(4 * g2 * g + h0 * g);
+    // the 4-lane part: rounds of partner distance 2 and 1 over h0
+    int i = 0;
+#pragma unroll
+    for (int hs = 2; hs >= 1; hs >>= 1, ++i) {
+      const int b = (h0 / hs) & 1;
+      const int hl = h0 % hs;
+      c.sgn[i] = b ? static_cast<T>(-1) : static_cast<T>(1);
+      c.rw[i] = (b && hl) ? root16<S, T>(hl * (8 / hs)) : cpx<T>{1, 0};
+    }
+  } else if constexpr (H > 1) {
     int i = 0;
 #pragma unroll
     for (int hs = H / 2; hs >= 1; hs >>= 1, ++i) {
@@ -545,6 +613,31 @@ __device__ __forceinline__ void xlane_rounds(cpx<T>* v, const LineCtx<E, H, S, T
   }
 }
 
+// Value of another lane (byte address src = 4*lane) through the LDS
+// crossbar; no LDS memory is used.
+__device__ __forceinline__ float lane_read(int src, float x) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(x)));
+}
+__device__ __forceinline__ double lane_read(int src, double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_ds_bpermute(src, static_cast<int>(b & 0xffffffffll));
+  const int hi = __builtin_amdgcn_ds_bpermute(src, static_cast<int>(b >> 32));
+  return __longlong_as_double((static_cast<long long>(hi) << 32) |
+                              (static_cast<long long>(lo) & 0xffffffffll));
+}
+
+// The radix-3 step of a 12-lane line: every lane forms its output c = g of
+// the DFT_3 over the three 4-lane groups (with the twiddle w_12^{h0*c}).
+template <int E, int H, int S, typename T>
+__device__ __forceinline__ void xlane_radix3(cpx<T>* v, const LineCtx<E, H, S, T>& c) {
+#pragma unroll
+  for (int k = 0; k < E; ++k) {
+    const cpx<T> p1 = {lane_read(c.src1, v[k].re), lane_read(c.src1, v[k].im)};
+    const cpx<T> p2 = {lane_read(c.src2, v[k].re), lane_read(c.src2, v[k].im)};
+    v[k] = cmac(cmac(cmul(v[k], c.a3[0]), p1, c.a3[1]), p2, c.a3[2]);
+  }
+}
+
 // One transform line of length N = E*H spread over H adjacent lanes of a
 // wavefront (h = position of the lane in its group). On entry lane h holds
 // x[h + H*j] in v[j] (j < E); on exit it holds X[k + E*bitrev(h)] in v[k].
@@ -568,7 +661,12 @@ __device__ __forceinline__ void line_fft(cpx<T>* v, const LineCtx<E, H, S, T>& c
 #pragma unroll
       for (int k = 1; k < E; ++k) v[k] = twmul<S>(v[k], c.rootN, c.rootN_lo, c.h * k);
     }
-    xlane_rounds<H / 2, 0, E, H, S, T>(v, c);
+    if constexpr (H == 12) {
+      xlane_radix3(v, c);
+      xlane_rounds<2, 0, E, H, S, T>(v, c);
+    } else {
+      xlane_rounds<H / 2, 0, E, H, S, T>(v, c);
+    }
   }
 }
 

@@ -31,6 +31,16 @@
 
 #include "device_common.hpp"
 
+// Compile-time overrides of the memory-level parallelism (0 = the defaults
+// below): blocks per round trip of the inverse fold, rows per round of the
+// forward x transforms.
+#ifndef FFTB_FOLD_BLOCKS
+#define FFTB_FOLD_BLOCKS 0
+#endif
+#ifndef FFTB_FWD_ROWS
+#define FFTB_FWD_ROWS 0
+#endif
+
 namespace fftb {
 
 
@@ -56,7 +66,8 @@ __device__ __forceinline__ int div_small(int n, int d, float inv_d) {
 // ---------------------------------------------------------------------------
 template <int S, typename T, int E, int H, bool MF>
 __device__ void k1r_task(const KArgs& a, int t) {
-  constexpr int L = log2_const<H>();
+  // lanes per line group: a line of 12 lanes takes a row of 16
+  constexpr int HG = lane_group<H>();
   const int s = find_sphere_k1r(a, t);
   const SphereDesc d = a.sph[s];
   const int lt = t - d.k1_start;
@@ -73,16 +84,18 @@ __device__ void k1r_task(const KArgs& a, int t) {
   cpx<T>* __restrict__ colbuf = reinterpret_cast<cpx<T>*>(a.col) + d.col_off + b0;
   const cpx<T>* rootz = reinterpret_cast<const cpx<T>*>(a.rootz);
   const cpx<T>* rootz_lo = reinterpret_cast<const cpx<T>*>(a.rootz_lo);
-  const int items = (nl << bcl) * H;
+  const int items = (nl << bcl) * HG;
   // with the matrix-core codelet whole waves take part: pad to 64 lanes
   const int iters = MF ? ((items + 63) & ~63) : items;
-  // the block size is a multiple of H: a thread keeps its lane position h
-  const int h = threadIdx.x % H;
+  // the block size is a multiple of HG: a thread keeps its lane position h;
+  // lanes past H in a 16-lane row of a 12-lane line only join the exchanges
+  const int h = threadIdx.x % HG;
+  const bool lane_on = h < H;
   const auto ctx = line_ctx<E, H, S, T>(h, rootz, rootz_lo);
   // NP lines per thread per round (two for short lines): the table lookups and
   // loads of all of them are issued before any is used
   constexpr int NP = (E <= 10 && !MF) ? 2 : 1;
-  const int q = bitrev_bits(h, L);
+  const int q = out_block<H>(lane_on ? h : 0);
   // with a.k1buf the sphere and the column region are addressed as buffers
   // (both below 4 GiB): one offset register per line, uniform z strides
   constexpr unsigned es = sizeof(cpx<T>);
@@ -100,9 +113,9 @@ __device__ void k1r_task(const KArgs& a, int t) {
     for (int p = 0; p < NP; ++p) {
       const int it = it0 + p * blockDim.x;
       // with the matrix-core codelet padded lanes still run the transform
-      ok[p] = MF ? it < items : it < iters;
-      const int iv = ok[p] ? it : h;
-      const int rest = iv / H;
+      ok[p] = (MF ? it < items : it < iters) && lane_on;
+      const int iv = (MF ? it < items : it < iters) ? it : h;
+      const int rest = iv / HG;
       bls[p] = rest & bmask;
       cc[p] = c0 + (rest >> bcl);
       slot[p] = cslot[cc[p]];
@@ -113,7 +126,7 @@ __device__ void k1r_task(const KArgs& a, int t) {
 #pragma unroll
       for (int p = 0; p < NP; ++p)
 #pragma unroll
-        for (int j = 0; j < E; ++j) g[p][j] = gidx[cc[p] * nz + h + H * j];
+        for (int j = 0; j < E; ++j) g[p][j] = ok[p] ? gidx[cc[p] * nz + h + H * j] : -1;
 #pragma unroll
       for (int p = 0; p < NP; ++p) {
         const int b = b0 + bls[p];
@@ -247,8 +260,9 @@ __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S) {
         for (int k = threadIdx.x; k < M; k += blockDim.x) ttw[k] = twf[k * r];
     }
     __syncthreads();
-    // two blocks per round trip when their values fit the register budget
-    constexpr bool kPair = M * sizeof(T) <= 64;
+    // NBF blocks per round trip (their loads are all issued before the first
+    // is accumulated; two measured best: four cost registers and time)
+    constexpr int NBF = FFTB_FOLD_BLOCKS > 0 ? FFTB_FOLD_BLOCKS : 2;
     // the plane's column scratch as a buffer (the host keeps it below 2 GiB):
     // a block's M loads share one offset register
     const __amdgpu_buffer_rsrc_t rs = buf_rsrc(colp);
@@ -280,27 +294,20 @@ __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S) {
       auto off_of = [&](int e) {
         return static_cast<unsigned>((e >> 10) * nbp + bl) * static_cast<unsigned>(sizeof(cpx<T>));
       };
-      for (int i = 0; i < nh; i += (kPair ? 2 : 1)) {
-        const int e0 = lst[i];
-        const unsigned o0 = off_of(e0);
-        cpx<T> v0[M];
-        if constexpr (kPair) {
-          const bool two = i + 1 < nh;
-          const int e1 = two ? lst[i + 1] : e0;
-          const unsigned o1 = off_of(e1);
-          cpx<T> v1[M];
+      for (int i = 0; i < nh; i += NBF) {
+        // past the list's end the last block is loaded again (cache hits) and
+        // accumulated with weight zero
+        int eb[NBF];
+        cpx<T> vb[NBF][M];
 #pragma unroll
-          for (int k = 0; k < M; ++k) {
-            v0[k] = buf_load(rs, colp, o0, k * slot_bytes);
-            v1[k] = buf_load(rs, colp, o1, k * slot_bytes);
-          }
-          accumulate(v0, e0 & 1023, true);
-          accumulate(v1, e1 & 1023, two);
-        } else {
+        for (int b = 0; b < NBF; ++b) {
+          eb[b] = lst[min(i + b, nh - 1)];
+          const unsigned o = off_of(eb[b]);
 #pragma unroll
-          for (int k = 0; k < M; ++k) v0[k] = buf_load(rs, colp, o0, k * slot_bytes);
-          accumulate(v0, e0 & 1023, true);
+          for (int k = 0; k < M; ++k) vb[b][k] = buf_load(rs, colp, o, k * slot_bytes);
         }
+#pragma unroll
+        for (int b = 0; b < NBF; ++b) accumulate(vb[b], eb[b] & 1023, i + b < nh);
       }
       if constexpr (std::is_same<T, double>::value) {
 #pragma unroll
@@ -453,31 +460,47 @@ __device__ __forceinline__ void fwd_x_rows(const KArgs& a, const cpx<T>* __restr
   const __amdgpu_buffer_rsrc_t gplane = buf_rsrc(gin + static_cast<int64_t>(z) * ny * nx * nb);
   const unsigned hstride =
       __builtin_amdgcn_readfirstlane(static_cast<unsigned>(H * nb) * sizeof(cpx<T>));
-  for (int rest = threadIdx.x / H; rest < nrest_p; rest += rstep) {
-    const bool valid = rest < nrest;
-    const int rv = valid ? rest : 0;
-    const int bl = rv & bmask, k2 = rv >> bcl;
-    const int y = r + n1 * k2;
-    const int b = b0 + bl;
-    const bool ld = valid && b < nb;
-    cpx<T> v[E];
-    if (a.plane32) {
-      const unsigned off =
-          static_cast<unsigned>((y * nx + h) * nb + b) * static_cast<unsigned>(sizeof(cpx<T>));
+  // RB rows per thread per round, the loads of all of them issued before the
+  // first is transformed (one measured best: batching two or four rows was
+  // slower at every benchmark shape)
+  constexpr int RB = FFTB_FWD_ROWS > 0 ? FFTB_FWD_ROWS : 1;
+  for (int rest0 = threadIdx.x / H; rest0 < nrest_p; rest0 += RB * rstep) {
+    cpx<T> v[RB][E];
+    int k2s[RB], bls[RB];
+    bool valid[RB];
 #pragma unroll
-      for (int j = 0; j < E; ++j)
-        v[j] = ld ? buf_load(gplane, gin, off, j * hstride) : cpx<T>{0, 0};
-    } else {
-      const cpx<T>* row = gin + static_cast<int64_t>(z * ny + y) * nx * nb + b;
+    for (int u = 0; u < RB; ++u) {
+      const int rest = rest0 + u * rstep;
+      valid[u] = rest < nrest;
+      const int rv = valid[u] ? rest : 0;
+      bls[u] = rv & bmask;
+      k2s[u] = rv >> bcl;
+      const int y = r + n1 * k2s[u];
+      const int b = b0 + bls[u];
+      const bool ld = valid[u] && b < nb;
+      if (a.plane32) {
+        const unsigned off =
+            static_cast<unsigned>((y * nx + h) * nb + b) * static_cast<unsigned>(sizeof(cpx<T>));
 #pragma unroll
-      for (int j = 0; j < E; ++j)
-        v[j] = ld ? row[static_cast<int64_t>(h + H * j) * nb] : cpx<T>{0, 0};
+        for (int j = 0; j < E; ++j)
+          v[u][j] = ld ? buf_load(gplane, gin, off, j * hstride) : cpx<T>{0, 0};
+      } else {
+        const cpx<T>* row = gin + static_cast<int64_t>(z * ny + y) * nx * nb + b;
+#pragma unroll
+        for (int j = 0; j < E; ++j)
+          v[u][j] = ld ? row[static_cast<int64_t>(h + H * j) * nb] : cpx<T>{0, 0};
+      }
     }
-    line_fft<E, H, -1, T, MF>(v, ctx);
-    if (!valid) continue;
 #pragma unroll
-    for (int k = 0; k < E; ++k)
-      if (xs[k] >= 0) S[xs[k] * sx + (k2 << bcl) + bl] = v[k];
+    for (int u = 0; u < RB; ++u) {
+      // rows past the padded count are skipped by whole waves
+      if (rest0 + u * rstep >= nrest_p) continue;
+      line_fft<E, H, -1, T, MF>(v[u], ctx);
+      if (!valid[u]) continue;
+#pragma unroll
+      for (int k = 0; k < E; ++k)
+        if (xs[k] >= 0) S[xs[k] * sx + (k2s[u] << bcl) + bls[u]] = v[u][k];
+    }
   }
 }
 
@@ -814,7 +837,9 @@ hipError_t launch_one(int which, const KArgs& a, int grid, int threads, size_t l
     hipLaunchKernelGGL((k1r_kernel<S, T, E, H, MF>), dim3(grid), dim3(threads), 0, st, a);
     return hipGetLastError();
   }
-  if constexpr (S < 0) {
+  if constexpr (H == 12) {
+    return hipErrorInvalidValue;  // 12-lane lines serve the column kernel only
+  } else if constexpr (S < 0) {
     if (a.fwd_cls) return launch_k2<S, T, E, H, MF, true, 0>(a, grid, threads, lds, st);
   } else {
     const bool pot = a.pot != nullptr;
@@ -829,12 +854,16 @@ hipError_t launch_one(int which, const KArgs& a, int grid, int threads, size_t l
     if (fold_m != 0) return hipErrorInvalidValue;
     if (pot) return launch_k2<S, T, E, H, MF, true, 0>(a, grid, threads, lds, st);
   }
-  if (fold_m != 0) return hipErrorInvalidValue;
-  return launch_k2<S, T, E, H, MF, false, 0>(a, grid, threads, lds, st);
+  if constexpr (H != 12) {
+    if (fold_m != 0) return hipErrorInvalidValue;
+    return launch_k2<S, T, E, H, MF, false, 0>(a, grid, threads, lds, st);
+  }
+  return hipErrorInvalidValue;
 }
 
 template <int S, typename T, int E, int H, bool MF>
 hipError_t attr_one(size_t lds) {
+  if constexpr (H == 12) return hipSuccess;  // no plane kernel for 12-lane lines
   hipError_t e = attr_k2<S, T, E, H, MF, false, 0>(lds);
   if (e == hipSuccess) e = attr_k2<S, T, E, H, MF, true, 0>(lds);
   if constexpr (S > 0 && fold_m_compiled(H, 8)) {
@@ -852,7 +881,7 @@ hipError_t attr_one(size_t lds) {
 // shape (the host picks one shape per axis).
 #define FFTB_REG_SHAPES(X)                                                         \
   X(4, 1, 0) X(5, 1, 0) X(6, 1, 0) X(8, 1, 0) X(9, 1, 0) X(10, 1, 0) X(12, 1, 0) \
-  X(15, 1, 0) X(16, 1, 0) X(5, 4, 0) X(6, 4, 0) X(45, 4, 0)                      \
+  X(15, 1, 0) X(16, 1, 0) X(5, 4, 0) X(6, 4, 0) X(45, 4, 0) X(15, 12, 0)         \
   X(4, 8, 1) X(12, 8, 1) X(16, 8, 1) X(18, 8, 1) X(20, 8, 1)                      \
   X(6, 16, 2) X(8, 16, 2) X(9, 16, 2) X(10, 16, 2) X(16, 16, 2)
 constexpr int kRegParts = 3;

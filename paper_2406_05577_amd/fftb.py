@@ -14,7 +14,8 @@ from typing import Optional, Sequence
 import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libfftb.so")
+# the in-tree build; FFTB_LIB may name another build of the same library
+LIB_PATH = os.environ.get("FFTB_LIB") or os.path.join(_PKG, "libfftb.so")
 
 FFTB_OK = 0
 FFTB_ERR_INVALID = -1
