@@ -35,6 +35,10 @@ bool mfma_shape_supported(bool fp64, int E, int H);
 bool fold_m_supported(int H, int m);
 hipError_t launch_combine(const KArgs& a, bool fp64, int grid, int threads, hipStream_t st);
 hipError_t static_scratch_ptr(void** out);
+bool bil_shape_supported(bool fp64, bool zaxis, int E, int H);
+hipError_t launch_bil(int which, const KArgs& a, bool inverse, bool fp64, int E, int H, int grid,
+                      int threads, size_t lds, hipStream_t st, int fold_m);
+hipError_t prepare_bil(bool fp64, int E, int H, size_t lds);
 hipError_t launch_zero_scratch(void* p, size_t bytes, hipStream_t st);
 }  // namespace fftb
 
@@ -82,6 +86,8 @@ struct DirCfg {
   int bc = 8, n1 = 1, m = 1, lx = 1, lc = 1, threads = 256;
   bool reg1 = false, reg2 = false;  // register path for the column / plane kernel
   bool mf1 = false, mf2 = false;    // DFT_16 stages on the matrix cores
+  bool bil1 = false, bil2 = false;  // band-inner lines (column / plane kernel)
+  int lds_twx = 0, zline = 0;       // band-inner plane kernel: twiddle table (bytes), spare line
   int e1 = 0, h1 = 0, e2 = 0, h2 = 0;
   bool class_par = false;           // plane tasks include the y class
   bool acc_lds = false;             // forward accumulators in LDS
@@ -249,17 +255,11 @@ int64_t band_stride(int64_t nb, int bc, int es) {
 // Slots of the padded layout stay below 2^21 (they are packed with the block
 // index), and one plane of the column scratch below 2 GiB (the fold addresses
 // it with 32-bit buffer offsets).
+int64_t padded_slots(const SphereTables& s, int M);
+
 bool fold_slots_fit(const fftb_plan_s& P, int M, int bc) {
   for (auto& s : P.sph) {
-    int64_t slots = 0;
-    for (int xi = 0; xi < s.nslab; ++xi) {
-      int cur = -1;
-      for (int c = s.slabstart[xi]; c < s.slabstart[xi + 1]; ++c)
-        if (s.col_y[c] / M != cur) {
-          cur = s.col_y[c] / M;
-          slots += M;
-        }
-    }
+    const int64_t slots = padded_slots(s, M);
     if (slots >= (int64_t{1} << 21)) return false;
     const int64_t nbp = band_stride(s.nb, bc, es_of(P.dtype));
     if (slots * nbp * es_of(P.dtype) >= (int64_t{1} << 31)) return false;
@@ -267,12 +267,74 @@ bool fold_slots_fit(const fftb_plan_s& P, int M, int bc) {
   return true;
 }
 
-// LDS of the inverse fold's staged tables: per slab n1 block entries and a
-// count, then n1 roots (hi and lo) of the class and its m twiddles.
+// LDS of the inverse fold's staged tables: per slab n1 block entries, a count
+// and the slab order, then n1 roots (hi and lo) of the class and its m
+// twiddles (FP32: hi and lo).
 size_t fold_table_bytes(const fftb_plan_s& P, int n1) {
   const size_t ints = ((static_cast<size_t>(P.max_nslab) * n1 + 3) & ~size_t{3}) +
-                      ((P.max_nslab + 3) & ~3);
-  return ints * 4 + static_cast<size_t>(2 * n1 + P.ny / n1) * es_of(P.dtype);
+                      2 * ((P.max_nslab + 3) & ~3);
+  return ints * 4 + static_cast<size_t>(2 * n1 + 2 * (P.ny / n1)) * es_of(P.dtype);
+}
+
+// Band-inner shape of a line of length n: positions H = 4 (complex64) or 8
+// (complex128), so that one line fills a wavefront with one 128-byte piece of
+// bands per row of lanes.
+bool bil_shape(int n, bool fp64, bool zaxis, int& E, int& H) {
+  const int h = fp64 ? 8 : 4;
+  if (n % h || !bil_shape_supported(fp64, zaxis, n / h, h)) return false;
+  E = n / h;
+  H = h;
+  return true;
+}
+
+// Column slots of one plane of a sphere when its columns sit in zero-padded
+// blocks of M consecutive y (M = 16 bounds every layout the plans use).
+int64_t padded_slots(const SphereTables& s, int M) {
+  int64_t slots = 0;
+  for (int xi = 0; xi < s.nslab; ++xi) {
+    int cur = -1;
+    for (int c = s.slabstart[xi]; c < s.slabstart[xi + 1]; ++c)
+      if (s.col_y[c] / M != cur) {
+        cur = s.col_y[c] / M;
+        slots += M;
+      }
+  }
+  return slots;
+}
+
+// The band-inner kernels address every grid plane, column plane and class
+// partial plane with 32-bit offsets (below 2 GiB) and every sphere's
+// coefficients and column region below 4 GiB.
+bool bil_regions_fit(const fftb_plan_s& P, int bw) {
+  const int64_t es = es_of(P.dtype);
+  for (const auto& sp : P.sph) {
+    const int64_t nbp = band_stride(sp.nb, bw, es);
+    const int64_t colplane = padded_slots(sp, 16) * nbp * es;
+    const int64_t zplane = static_cast<int64_t>(sp.nslab) * P.ny * nbp * es;
+    const int64_t gplane = static_cast<int64_t>(P.nx) * P.ny * sp.nb * es;
+    if (std::max(colplane, std::max(zplane, gplane)) >= (int64_t{1} << 31)) return false;
+    if (sp.ns * sp.nb * es >= 0xffffffffLL || colplane * P.nz >= 0xffffffffLL) return false;
+  }
+  return true;
+}
+
+// LDS of the band-inner plane kernel with class length m: the class slab
+// (max_nslab lines of m x bw values, plus the spare line), then (inverse) the
+// fold tables, then the E x H twiddle table of the x lines.
+size_t plane_lds_bil(const fftb_plan_s& P, int n1, int bw, int e2, int h2, bool inverse,
+                     int& sx, int& tab_at, int& tw_at) {
+  const int m = P.ny / n1;
+  sx = m * bw;
+  size_t b = static_cast<size_t>(P.max_nslab + 1) * sx * es_of(P.dtype);
+  b = (b + 15) & ~size_t{15};
+  tab_at = static_cast<int>(b);
+  // inverse: the fold tables; forward: the class twiddles (FP32 hi and lo)
+  if (inverse) b = (b + fold_table_bytes(P, n1) + 15) & ~size_t{15};
+  else b = (b + static_cast<size_t>(2 * m) * es_of(P.dtype) + 15) & ~size_t{15};
+  tw_at = static_cast<int>(b);
+  // the twiddle table (lines of more than one position), then the slab-line
+  // offsets of the nx x positions
+  return b + (h2 > 1 ? static_cast<size_t>(e2) * h2 * 16 : 0) + static_cast<size_t>(P.nx) * 4;
 }
 
 // Cut a sphere's slabs into Q contiguous ranges with about equal column counts.
@@ -311,13 +373,79 @@ fftb_status choose_dir(fftb_plan_s& P, int d, const fftb_dir_tuning& t) {
   if (threads != 64 && threads != 128 && threads != 256 && threads != 512)
     return fail(FFTB_ERR_INVALID, "threads must be 64, 128, 256 or 512");
   if (n1 != 0 && (n1 < 1 || P.ny % n1)) return fail(FFTB_ERR_INVALID, "y_classes must divide ny");
-  if (t.path < 0 || t.path > 2) return fail(FFTB_ERR_INVALID, "path must be 0, 1 or 2");
+  if (t.path < 0 || t.path > 3) return fail(FFTB_ERR_INVALID, "path must be 0, 1, 2 or 3");
   if (t.acc < 0 || t.acc > 3) return fail(FFTB_ERR_INVALID, "acc must be 0, 1, 2 or 3");
   if (t.splits < 0 || t.splits > 8) return fail(FFTB_ERR_INVALID, "splits must be in [1, 8]");
   if (t.col_tile < 0) return fail(FFTB_ERR_INVALID, "col_tile must be >= 1");
   if (t.x_rows < 0) return fail(FFTB_ERR_INVALID, "x_rows must be >= 1");
   D.bc = bc;
   D.threads = threads;
+  D.bil1 = D.bil2 = false;
+  // ---- band-inner lines (path 3, and the default where the shapes exist):
+  // the band chunk is one 128-byte piece
+  const int bw = fp64 ? 8 : 16;
+  const bool bil_ok = (t.path == 0 || t.path == 3) && (t.band_chunk == 0 || t.band_chunk == bw) &&
+                      (t.lanes == 0) && !(P.flags & FFTB_PLAN_MFMA) && bil_regions_fit(P, bw);
+  if (bil_ok) {
+    int e1 = 0, h1 = 0, e2 = 0, h2 = 0;
+    // the column kernel takes the band-inner shape of z, else a register shape
+    const bool z_bil = bil_shape(P.nz, fp64, true, e1, h1);
+    const bool z_ok = z_bil || reg_shape(P.nz, fp64, e1, h1, 0, true);
+    const bool x_ok = bil_shape(P.nx, fp64, false, e2, h2);
+    if (z_ok && x_ok) {
+      // inverse: the fewest classes whose slab fits (every class re-reads the
+      // plane's columns) with a register fold of length 8 or 16; forward: the
+      // fewest classes with a combine codelet, two workgroups per CU if possible
+      int best_n1 = 0, sx = 0, tab_at = 0, tw_at = 0;
+      size_t best_b = 0;
+      for (size_t cap : {(n1 || inverse) ? kLdsMax : kLdsMax / 2, kLdsMax}) {
+        for (int c = 1; c <= P.ny && !best_n1; ++c) {
+          if (P.ny % c || (n1 && c != n1)) continue;
+          const int m = P.ny / c;
+          if (inverse ? !(m == 8 || m == 16) || !fold_slots_fit(P, m, bw)
+                      : !single_codelet(m) || !single_codelet(c))
+            continue;
+          const size_t b = plane_lds_bil(P, c, bw, e2, h2, inverse, sx, tab_at, tw_at);
+          if (b > cap) continue;
+          best_n1 = c;
+          best_b = b;
+        }
+        if (best_n1) break;
+      }
+      if (best_n1) {
+        plane_lds_bil(P, best_n1, bw, e2, h2, inverse, sx, tab_at, tw_at);
+        D.bc = bw;
+        D.bil1 = z_bil;
+        D.bil2 = D.reg1 = D.reg2 = true;
+        D.e1 = e1;
+        D.h1 = h1;
+        D.e2 = e2;
+        D.h2 = h2;
+        D.lc = t.col_tile ? t.col_tile
+                          : z_bil ? 8 * std::max(1, 64 / (bw * h1))
+                                  : std::max(1, 512 / (bw * (h1 == 12 ? 16 : h1)));
+        D.lds1 = 0;
+        D.n1 = best_n1;
+        D.m = P.ny / best_n1;
+        D.sx = sx;
+        D.lds2 = best_b;
+        D.lds_tab = tab_at;
+        D.lds_twx = tw_at;
+        D.zline = P.max_nslab * sx;
+        D.class_par = true;
+        D.fwd_cls = !inverse;
+        D.fold_m = inverse ? D.m : 0;
+        D.acc_lds = false;
+        D.nsplit = 1;
+        std::vector<int> rad;
+        plan_radices(D.m, rad);
+        make_axis_plan(D.m, rad, D.ay);
+        if (!t.threads && D.lds2 > kLdsMax / 2) D.threads = 512;
+        return FFTB_OK;
+      }
+    }
+    if (t.path == 3) return fail(FFTB_ERR_UNSUPPORTED, "no band-inner line shape or class split fits");
+  }
   // ---- column kernel
   int e1 = 0, h1 = 0;
   if (t.lanes != 0 && t.lanes != 1 && t.lanes != 4 && t.lanes != 8 && t.lanes != 12 &&
@@ -798,7 +926,7 @@ fftb_status device_setup(fftb_plan_s& P, hipStream_t st) {
     return fail(FFTB_ERR_HIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
   for (auto& D : P.dir) {
     if (!D.reg2) continue;
-    e = prepare_reg(fp64, D.e2, D.h2, r2, D.mf2);
+    e = D.bil2 ? prepare_bil(fp64, D.e2, D.h2, r2) : prepare_reg(fp64, D.e2, D.h2, r2, D.mf2);
     if (e != hipSuccess)
       return fail(FFTB_ERR_HIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
   }
@@ -863,6 +991,8 @@ KArgs make_args(const fftb_plan_s& P, const DirCfg& D, const void* in, void* out
   a.slab_blk = P.d_slabblk;
   a.slab_nblk = P.d_slabnblk;
   a.lds_tab = D.lds_tab;
+  a.lds_twx = D.lds_twx;
+  a.zline = D.zline;
   a.slab_order = P.d_slaborder;
   a.twx = P.d_twx;
   a.twy = D.d_twy;
@@ -951,6 +1081,10 @@ hipError_t enqueue(fftb_plan_s* P, const KArgs& a, const DirCfg& D, bool inverse
     const bool reg = which == 1 ? D.reg1 : D.reg2;
     if (which == 3) {
       e = launch_combine(a, fp64, g3, 256, st);
+    } else if (which == 1 ? D.bil1 : D.bil2) {
+      e = launch_bil(which, a, inverse, fp64, which == 1 ? D.e1 : D.e2, which == 1 ? D.h1 : D.h2,
+                     which == 1 ? g1 : g2, which == 1 ? 256 : D.threads, which == 1 ? 0 : D.lds2, st,
+                     which == 1 ? 0 : D.fold_m);
     } else if (reg) {
       e = launch_reg(which, a, inverse, fp64, which == 1 ? D.e1 : D.e2, which == 1 ? D.h1 : D.h2,
                      which == 1 ? g1 : g2, which == 1 ? std::min(D.threads, 256) : D.threads,
@@ -1035,8 +1169,8 @@ void log_plan(const fftb_plan_s& P) {
                  "columns/task, %d tasks), plane kernel %s (%dx%d, LDS %zu B, %d tasks)%s%s, "
                  "fold m %d\n",
                  d == 0 ? "inverse" : "forward", D.bc, D.n1, D.m, D.threads,
-                 D.reg1 ? "register" : "LDS-stage", D.e1, D.h1, D.lc, D.k1_tasks,
-                 D.reg2 ? "register" : "LDS-stage", D.e2, D.h2, D.lds2, D.k2_tasks,
+                 D.bil1 ? "band-inner" : D.reg1 ? "register" : "LDS-stage", D.e1, D.h1, D.lc, D.k1_tasks,
+                 D.bil2 ? "band-inner" : D.reg2 ? "register" : "LDS-stage", D.e2, D.h2, D.lds2, D.k2_tasks,
                  D.fwd_cls ? ", class partials + combine" : "", D.mf2 || D.mf1 ? ", matrix-core DFT_16" : "",
                  D.fold_m);
   }
@@ -1129,7 +1263,9 @@ struct DirKey {
   bool operator==(const DirKey& o) const { return std::memcmp(v, o.v, sizeof v) == 0; }
 };
 DirKey dir_key(const DirCfg& D, bool inverse) {
-  DirKey k = {{D.bc, D.n1, D.threads, (D.reg1 ? 1 : 0) | (D.reg2 ? 2 : 0), D.reg2 ? D.h2 : D.lx,
+  DirKey k = {{D.bc, D.n1, D.threads,
+               (D.reg1 ? 1 : 0) | (D.reg2 ? 2 : 0) | (D.bil1 ? 4 : 0) | (D.bil2 ? 8 : 0),
+               D.reg2 ? D.h2 : D.lx,
                D.lc, inverse ? 0 : (D.fwd_cls ? 3 : D.acc_lds ? 1 : 2), D.nsplit, D.h1}};
   return k;
 }
@@ -1395,10 +1531,10 @@ fftb_status fftb_plan_create(fftb_plan* out, const int32_t dims[3], const fftb_s
       o.x_rows = D.lx;
       o.col_tile = D.lc;
       o.threads = D.threads;
-      o.path = (D.reg1 && D.reg2) ? 2 : (D.reg1 || D.reg2) ? 0 : 1;
+      o.path = D.bil2 ? 3 : (D.reg1 && D.reg2) ? 2 : (D.reg1 || D.reg2) ? 0 : 1;
       o.acc = d == 0 ? 0 : D.fwd_cls ? 3 : (D.reg2 && D.acc_lds) ? 1 : 2;
       o.splits = D.nsplit;
-      o.lanes = D.reg2 ? D.h2 : (D.reg1 ? D.h1 : 0);
+      o.lanes = D.bil2 ? 0 : D.reg2 ? D.h2 : (D.reg1 ? D.h1 : 0);
     }
     if (!(flags & FFTB_PLAN_HOST_ONLY)) {
       const size_t cap = device_byte_cap();

@@ -1,0 +1,153 @@
+// Band-inner transform lines for gfx950.
+//
+// The grid, the sphere and the column scratch all hold a band vector per point
+// (band fastest). A band-inner line keeps that order in the lanes of a
+// wavefront: lane = bl + BW*h (+ BW*H*i for the i-th line of a wave), with BW
+// bands per row of lanes such that BW values are one 128-byte piece (16
+// complex64 or 8 complex128 values). A line of length N = E*H lives in H
+// positions h of E values each; every global load or store of a row of BW
+// lanes is then one whole 128-byte piece, which measured 1.3x (stores) and
+// 1.8x (loads) faster than pieces of 32 bytes on MI355X.
+//
+// The transform is the Cooley-Tukey split N = E*H (Section 2.1): DFT_E in
+// registers, twiddles w_N^{h*k} read from a table in LDS (the E*H entries are
+// the same for every line, and the lanes of a row read the same entry), then
+// log2(H) radix-2 rounds across the positions, each lane fetching its partner's
+// value through the LDS crossbar.
+#pragma once
+
+#include "device_common.hpp"
+
+namespace fftb {
+
+// bands per 128-byte piece
+template <typename T>
+constexpr int band_width() {
+  return 128 / static_cast<int>(2 * sizeof(T));
+}
+
+// One twiddle of the LDS table: the FP64 value, or the FP32 hi and lo parts.
+template <typename T>
+struct TwEntry;
+template <>
+struct alignas(16) TwEntry<double> {
+  double re, im;
+};
+template <>
+struct alignas(16) TwEntry<float> {
+  float re, im, lre, lim;
+};
+
+// Fill tab[h*E + k] = w_N^{S*h*k} (N = E*H) from the forward-sign root table
+// of length N (FP32: hi and lo tables). Block-cooperative; the caller
+// synchronises before use.
+template <int S, typename T>
+__device__ void bl_fill_twiddles(TwEntry<T>* tab, const cpx<T>* __restrict__ root,
+                                 const cpx<T>* __restrict__ root_lo, int E, int H) {
+  for (int i = threadIdx.x; i < E * H; i += blockDim.x) {
+    const int h = i / E, k = i - (i / E) * E;
+    const cpx<T> w = root[h * k];
+    const T sg = S > 0 ? static_cast<T>(-1) : static_cast<T>(1);
+    TwEntry<T> e;
+    e.re = w.re;
+    e.im = sg * w.im;
+    if constexpr (std::is_same<T, float>::value) {
+      const cpx<T> l = root_lo[h * k];
+      e.lre = l.re;
+      e.lim = sg * l.im;
+    }
+    tab[i] = e;
+  }
+}
+
+template <int E, int H, int S, typename T>
+struct BLineCtx {
+  static constexpr int kRounds = H > 1 ? log2_const<H>() : 1;
+  const TwEntry<T>* tw;  // row h of the LDS table
+  T sgn[kRounds];
+  cpx<T> rw[kRounds];
+};
+
+// Context of the lane at position h of its line; tab is the LDS table.
+template <int E, int H, int S, typename T>
+__device__ __forceinline__ BLineCtx<E, H, S, T> bline_ctx(int h, const TwEntry<T>* tab) {
+  BLineCtx<E, H, S, T> c;
+  c.tw = tab + h * E;
+  if constexpr (H > 1) {
+    int i = 0;
+#pragma unroll
+    for (int hs = H / 2; hs >= 1; hs >>= 1, ++i) {
+      const int b = (h / hs) & 1;
+      const int hl = h % hs;
+      c.sgn[i] = b ? static_cast<T>(-1) : static_cast<T>(1);
+      c.rw[i] = (b && hl) ? root16<S, T>(hl * (8 / hs)) : cpx<T>{1, 0};
+    }
+  }
+  return c;
+}
+
+// Radix-2 rounds across the positions: partner distance hs positions = BW*hs
+// lanes. Each lane fetches its partner's value through the LDS crossbar
+// (ds_bpermute: no LDS memory, no VALU moves), then the lower lane of a pair
+// keeps own + partner, the upper one forms partner - own and multiplies it by
+// the round twiddle.
+template <int HS, int I, int E, int H, int S, typename T>
+__device__ __forceinline__ void bl_rounds(cpx<T>* v, const BLineCtx<E, H, S, T>& c) {
+  if constexpr (HS >= 1) {
+    constexpr int D = HS * band_width<T>();
+    const T sg = c.sgn[I];
+    const int src = ((threadIdx.x & 63) ^ D) << 2;
+    // in groups of four values, so that the fetched values do not all stay live
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const T pr = lane_read(src, v[k].re), pi = lane_read(src, v[k].im);
+      v[k] = {ffma(sg, v[k].re, pr), ffma(sg, v[k].im, pi)};
+      if ((k & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    }
+    if constexpr (HS > 1) {
+      const cpx<T> w = c.rw[I];
+#pragma unroll
+      for (int k = 0; k < E; ++k) v[k] = cmul(v[k], w);
+    }
+    bl_rounds<HS / 2, I + 1, E, H, S, T>(v, c);
+  }
+}
+
+// One band-inner line: on entry the lane at position h holds x[h + H*j] in
+// v[j] (j < E); on exit it holds X[k + E*bitrev(h)] in v[k]. Every lane of the
+// wavefront must take part (lanes of a line that has no data transform zeros).
+template <int E, int H, int S, typename T>
+__device__ __forceinline__ void bline_fft(cpx<T>* v, const BLineCtx<E, H, S, T>& c) {
+  dft<E, S>(v);
+  if constexpr (H > 1) {
+    // in groups of four: the scheduler would otherwise issue every table read
+    // at once and keep all E-1 twiddles live beside the line
+#pragma unroll
+    for (int k = 1; k < E; ++k) {
+      const TwEntry<T> w = c.tw[k];
+      if constexpr (std::is_same<T, float>::value)
+        v[k] = cmul_hl(v[k], cpx<float>{w.re, w.im}, cpx<float>{w.lre, w.lim});
+      else
+        v[k] = cmul(v[k], cpx<double>{w.re, w.im});
+      if ((k & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    }
+    bl_rounds<H / 2, 0, E, H, S, T>(v, c);
+  }
+}
+
+// Positions of a lane: band bl of the chunk, position h on its line, and the
+// line i of the wave (when one line uses only part of the wavefront).
+template <typename T, int H>
+struct BLane {
+  static constexpr int BW = band_width<T>();
+  static constexpr int LPW = 64 / (BW * H);  // lines per wavefront
+  int bl, h, sub;
+  __device__ __forceinline__ BLane() {
+    const int lane = threadIdx.x & 63;
+    bl = lane & (BW - 1);
+    h = (lane / BW) % H;
+    sub = lane / (BW * H);
+  }
+};
+
+}  // namespace fftb

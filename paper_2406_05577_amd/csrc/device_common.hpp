@@ -94,6 +94,16 @@ __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, cpx<float> v
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2i, v), r, voff, soff, 0);
 }
 
+// Non-temporal (streaming) stores: cache policy bit 1 (nt on gfx950).
+__device__ __forceinline__ void buf_store_nt(__amdgpu_buffer_rsrc_t r, cpx<double> v, unsigned voff) {
+  typedef int v4i __attribute__((ext_vector_type(4)));
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4i, v), r, voff, 0, 2);
+}
+__device__ __forceinline__ void buf_store_nt(__amdgpu_buffer_rsrc_t r, cpx<float> v, unsigned voff) {
+  typedef int v2i __attribute__((ext_vector_type(2)));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2i, v), r, voff, 0, 2);
+}
+
 // u + v*w with fused multiply-adds
 template <typename T>
 __device__ __forceinline__ cpx<T> cmac(cpx<T> u, cpx<T> v, cpx<T> w) {
@@ -318,6 +328,14 @@ __device__ __forceinline__ void dft(cpx<T>* v) {
     dft_ab<16, 3, S>(v);
   } else if constexpr (R == 64) {
     dft_ab<8, 8, S>(v);
+  } else if constexpr (R == 72) {
+    dft_ab<8, 9, S>(v);
+  } else if constexpr (R == 96) {
+    dft_ab<16, 6, S>(v);
+  } else if constexpr (R == 128) {
+    dft_ab<16, 8, S>(v);
+  } else if constexpr (R == 144) {
+    dft_ab<16, 9, S>(v);
   } else {
     static_assert(R == 1, "unsupported radix");
   }

@@ -54,6 +54,8 @@ struct KArgs {
   int lds_P, lds_X0, lds_X1;  // element offsets of LDS regions (S starts at 0)
   int lds_acc;       // element offset of the forward column accumulators
   int lds_tab;       // byte offset of the inverse fold's block lists and roots
+  int lds_twx;       // byte offset of the band-inner x twiddle table (plane kernel)
+  int zline;         // element offset of the spare class-slab line (band-inner x lines)
   int acc_lds;       // forward plane kernel accumulates columns in LDS
   int sx;            // element stride between slab lines of the class slab
   int nsplit;        // forward plane tasks per (plane, chunk): slab ranges with their columns

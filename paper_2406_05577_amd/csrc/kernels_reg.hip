@@ -1,11 +1,49 @@
 // Register-path dispatch: shape tables and the launchers the host calls. The
 // kernels themselves are templates in kernels_reg.hpp, instantiated in the
 // reg_*.hip translation units.
-#include "kernels_reg.hpp"
+#include "kernels_bil.hpp"
 
 namespace fftb {
 
 FFTB_REG_DECL_ALL(extern)
+FFTB_BIL_DECL(extern, +1, float)
+FFTB_BIL_DECL(extern, -1, float)
+FFTB_BIL_DECL(extern, +1, double)
+FFTB_BIL_DECL(extern, -1, double)
+
+// Band-inner shapes: z lines (column kernel) or x lines (plane kernel).
+bool bil_shape_supported(bool fp64, bool zaxis, int E, int H) {
+#define FFTB_CHK(e, h) if (E == e && H == h) return true;
+  if (fp64) {
+    if (zaxis) { FFTB_BIL_Z_F64(FFTB_CHK) } else { FFTB_BIL_X_F64(FFTB_CHK) }
+  } else {
+    if (zaxis) { FFTB_BIL_Z_F32(FFTB_CHK) } else { FFTB_BIL_X_F32(FFTB_CHK) }
+  }
+#undef FFTB_CHK
+  return false;
+}
+
+// which: 1 = column kernel (E, H of the z axis), 2 = plane kernel (E, H of x)
+hipError_t launch_bil(int which, const KArgs& a, bool inverse, bool fp64, int E, int H, int grid,
+                      int threads, size_t lds, hipStream_t st, int fold_m) {
+  if (fp64)
+    return inverse ? bil_dispatch<+1, double>(which, a, E, H, grid, threads, lds, st, fold_m, false)
+                   : bil_dispatch<-1, double>(which, a, E, H, grid, threads, lds, st, fold_m, false);
+  return inverse ? bil_dispatch<+1, float>(which, a, E, H, grid, threads, lds, st, fold_m, false)
+                 : bil_dispatch<-1, float>(which, a, E, H, grid, threads, lds, st, fold_m, false);
+}
+
+// Allow the band-inner plane kernels of an x shape `lds` bytes of dynamic LDS.
+hipError_t prepare_bil(bool fp64, int E, int H, size_t lds) {
+  KArgs dummy{};
+  hipError_t e;
+  if (fp64) {
+    e = bil_dispatch<+1, double>(2, dummy, E, H, 0, 0, lds, nullptr, 0, true);
+    return e != hipSuccess ? e : bil_dispatch<-1, double>(2, dummy, E, H, 0, 0, lds, nullptr, 0, true);
+  }
+  e = bil_dispatch<+1, float>(2, dummy, E, H, 0, 0, lds, nullptr, 0, true);
+  return e != hipSuccess ? e : bil_dispatch<-1, float>(2, dummy, E, H, 0, 0, lds, nullptr, 0, true);
+}
 
 hipError_t launch_combine(const KArgs& a, bool fp64, int grid, int threads, hipStream_t st) {
   if (fp64)

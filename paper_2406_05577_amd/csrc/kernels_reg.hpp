@@ -29,6 +29,7 @@
 
 #include <type_traits>
 
+#include "bline.hpp"
 #include "device_common.hpp"
 
 // Compile-time overrides of the memory-level parallelism (0 = the defaults
@@ -200,12 +201,140 @@ __device__ void k1r_task(const KArgs& a, int t) {
 }
 
 // ---------------------------------------------------------------------------
+// x transforms of the class rows y = r + n1*k2 (k2 < m) on band-inner lines:
+// one line (one row, all bands of the chunk) per wavefront, or two for
+// positions of half a wavefront. The band chunk is one 128-byte piece, so
+// every grid access of a row of lanes is a whole piece.
+//
+// Inverse: the row's occupied x values come from the class slab S[xi][k2][bl]
+// in LDS (zero at the other x), the line is transformed, and the whole row is
+// written to plane z of the grid (times the potential with POT).
+template <typename T, int E, int H, bool POT>
+__device__ __forceinline__ void bl_inv_x(const KArgs& a, const SphereDesc& d, const cpx<T>* S,
+                                         const TwEntry<T>* tab, const int* xo, int z, int r,
+                                         int b0) {
+  using Lane = BLane<T, H>;
+  const Lane ln;
+  // opaque lane position: the line context is formed per task instead of being
+  // hoisted out of the persistent loop, where it would stay live across the fold
+  int h = ln.h;
+  asm volatile("" : "+v"(h));
+  const int q = bitrev_bits(h, log2_const<H>());
+  const auto ctx = bline_ctx<E, H, +1, T>(h, tab);
+  const int nx = a.nx, ny = a.ny, nb = d.nb, n1 = a.n1, m = a.m, bcl = a.bcl;
+  cpx<T>* __restrict__ gout = reinterpret_cast<cpx<T>*>(a.out) + d.grid_off;
+  const __amdgpu_buffer_rsrc_t gplane = buf_rsrc(gout + static_cast<int64_t>(z) * ny * nx * nb);
+  const unsigned xstride =
+      __builtin_amdgcn_readfirstlane(static_cast<unsigned>(nb) * sizeof(cpx<T>));
+  const int wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+  const int b = b0 + ln.bl;
+  for (int base = wave * Lane::LPW; base < m; base += nwave * Lane::LPW) {
+    const int k2 = base + ln.sub;
+    const bool valid = k2 < m;
+    const int y = r + n1 * (valid ? k2 : 0);
+    T vp[E];
+    if constexpr (POT) {
+      const T* __restrict__ vrow =
+          reinterpret_cast<const T*>(a.pot) + static_cast<int64_t>(z * ny + y) * nx;
+#pragma unroll
+      for (int k = 0; k < E; ++k) vp[k] = vrow[k + E * q];
+    }
+    // the row's values: x = h + H*j from its slab line (the spare zero line
+    // for x without a slab), in groups of eight so that the offsets read from
+    // the table do not all stay live
+    const cpx<T>* row = S + (k2 << bcl) + ln.bl;
+    cpx<T> v[E];
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      v[j] = row[xo[h + H * j]];
+      if ((j & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+    }
+    bline_fft<E, H, +1, T>(v, ctx);
+    if constexpr (POT) {
+#pragma unroll
+      for (int k = 0; k < E; ++k) v[k] = cscale(v[k], vp[k]);
+    }
+    if (valid && b < nb) {
+      // (band-inner plans keep every grid plane below 2 GiB: 32-bit offsets)
+      // Non-temporal stores: the grid is not read again by this kernel, and
+      // streaming it past the L2 keeps the plane's columns there for the
+      // other classes' folds (measured 5 % (complex64) to 11 % (complex128)
+      // faster). A running lane offset: per-store scalar offsets k*xstride would be
+      // hoisted out of the row loop as E live scalar registers
+      unsigned o =
+          static_cast<unsigned>((y * nx + E * q) * nb + b) * static_cast<unsigned>(sizeof(cpx<T>));
+#pragma unroll
+      for (int k = 0; k < E; ++k) {
+        buf_store_nt(gplane, v[k], o);
+        o += xstride;
+        asm volatile("" : "+v"(o));
+      }
+    }
+  }
+}
+
+// Forward: the row is read from plane z of the grid, transformed, and its
+// occupied x values are kept in the class slab S[xi][k2][bl] (the others land
+// in the spare line).
+template <typename T, int E, int H>
+__device__ __forceinline__ void bl_fwd_x(const KArgs& a, const SphereDesc& d, cpx<T>* S,
+                                         const TwEntry<T>* tab, const int* xo, int z, int r,
+                                         int b0) {
+  using Lane = BLane<T, H>;
+  const Lane ln;
+  int h = ln.h;
+  asm volatile("" : "+v"(h));
+  const int q = bitrev_bits(h, log2_const<H>());
+  const auto ctx = bline_ctx<E, H, -1, T>(h, tab);
+  const int nx = a.nx, ny = a.ny, nb = d.nb, n1 = a.n1, m = a.m, bcl = a.bcl;
+  const cpx<T>* __restrict__ gin = reinterpret_cast<const cpx<T>*>(a.in) + d.grid_off;
+  const __amdgpu_buffer_rsrc_t gplane = buf_rsrc(gin + static_cast<int64_t>(z) * ny * nx * nb);
+  const unsigned hstride =
+      __builtin_amdgcn_readfirstlane(static_cast<unsigned>(H * nb) * sizeof(cpx<T>));
+  const int wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+  const int b = b0 + ln.bl;
+  for (int base = wave * Lane::LPW; base < m; base += nwave * Lane::LPW) {
+    const int k2 = base + ln.sub;
+    const bool valid = k2 < m;
+    const int y = r + n1 * (valid ? k2 : 0);
+    const bool ld = valid && b < nb;
+    cpx<T> v[E];
+    unsigned o = static_cast<unsigned>((y * nx + h) * nb + b) * static_cast<unsigned>(sizeof(cpx<T>));
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      v[j] = ld ? buf_load(gplane, gin, o, 0) : cpx<T>{0, 0};
+      o += hstride;
+      asm volatile("" : "+v"(o));
+    }
+    bline_fft<E, H, -1, T>(v, ctx);
+    if (valid) {
+      cpx<T>* row = S + (k2 << bcl) + ln.bl;
+#pragma unroll
+      for (int k = 0; k < E; ++k) {
+        row[xo[k + E * q]] = v[k];
+        if ((k & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+  }
+}
+
+// Stage the slab-line offsets of the x positions of sphere d in LDS:
+// xo[x] = xi*sx for the slab xi of x, the spare line for x without a slab.
+__device__ __forceinline__ void bl_stage_xoff(const KArgs& a, const SphereDesc& d, int* xo) {
+  const int32_t* __restrict__ xinv = a.xinv + d.xinv_off;
+  for (int x = threadIdx.x; x < a.nx; x += blockDim.x) {
+    const int xi = xinv[x];
+    xo[x] = xi >= 0 ? xi * a.sx : a.zline;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // M > 0: the class length m = M is a compile-time constant and the column
 // slots are laid out in zero-padded blocks of M consecutive y per slab; one
 // thread folds and transforms a whole (slab, band) line in registers.
 // M == 0: generic fold.
-template <typename T, int E, int H, bool MF, int M, bool POT>
-__device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S) {
+template <typename T, int E, int H, bool MF, int M, bool POT, bool BL>
+__device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S, const TwEntry<T>* tab, int* xo) {
   constexpr int L = log2_const<H>();
   const int s = find_sphere_k2r(a, t);
   const SphereDesc d = a.sph[s];
@@ -235,16 +364,19 @@ __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S) {
     // list (slot << 10 | tb) and the roots w_n1^{+tb*r} are staged in LDS.
     int32_t* tl = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(S) + a.lds_tab);
     int32_t* tn = tl + ((nslab * n1 + 3) & ~3);  // 16-byte aligned regions
-    cpx<T>* troot = reinterpret_cast<cpx<T>*>(tn + ((nslab + 3) & ~3));
-    // the class twiddles w_ny^{k*r}, k < M (hi, then lo for FP32)
-    // FP64: the class twiddles w_ny^{k*r}, k < M (staging them measured
-    // slower for the FP32 hi/lo pairs, which keep reading the global table)
+    int32_t* tord = tn + ((nslab + 3) & ~3);     // the slab order
+    cpx<T>* troot = reinterpret_cast<cpx<T>*>(tord + ((nslab + 3) & ~3));
+    // the class twiddles w_ny^{k*r}, k < M (FP32: hi and lo of each)
     cpx<T>* ttw = troot + 2 * n1;
     {
       const int32_t* __restrict__ blk = a.slab_blk + d.sl_off * n1;
       const int32_t* __restrict__ nblk = a.slab_nblk + d.sl_off;
+      const int32_t* __restrict__ ord = a.slab_order + d.sl_off;
       for (int i = threadIdx.x; i < nslab * n1; i += blockDim.x) tl[i] = blk[i];
-      for (int i = threadIdx.x; i < nslab; i += blockDim.x) tn[i] = nblk[i];
+      for (int i = threadIdx.x; i < nslab; i += blockDim.x) {
+        tn[i] = nblk[i];
+        tord[i] = ord[i];
+      }
       for (int tb = threadIdx.x; tb < n1; tb += blockDim.x) {
         const int idx = M * ((tb * r) % n1);  // w_n1^{tb*r} = w_ny^{M*((tb*r) mod n1)}
         cpx<T> w = twf[idx];
@@ -256,8 +388,15 @@ __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S) {
           troot[2 * tb + 1] = wl;
         }
       }
-      if constexpr (std::is_same<T, double>::value)
-        for (int k = threadIdx.x; k < M; k += blockDim.x) ttw[k] = twf[k * r];
+      for (int k = threadIdx.x; k < M; k += blockDim.x) {
+        if constexpr (std::is_same<T, double>::value) {
+          ttw[k] = twf[k * r];
+        } else {
+          ttw[2 * k] = twf[k * r];
+          ttw[2 * k + 1] = twfl[k * r];
+        }
+      }
+      if constexpr (BL) bl_stage_xoff(a, d, xo);
     }
     __syncthreads();
     // NBF blocks per round trip (their loads are all issued before the first
@@ -268,11 +407,10 @@ __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S) {
     const __amdgpu_buffer_rsrc_t rs = buf_rsrc(colp);
     const unsigned slot_bytes =
         __builtin_amdgcn_readfirstlane(static_cast<unsigned>(nbp) * sizeof(cpx<T>));
-    const int32_t* __restrict__ order = a.slab_order + d.sl_off;
     const int nlines = nslab << bcl;
     for (int it = threadIdx.x; it < nlines; it += blockDim.x) {
       const int bl = it & bmask;
-      const int xi = order[it >> bcl];
+      const int xi = tord[it >> bcl];
       const int nh = tn[xi];
       const int32_t* lst = tl + xi * n1;
       cpx<T> u[M];
@@ -314,7 +452,7 @@ __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S) {
         for (int k = 1; k < M; ++k) u[k] = twmul<+1>(u[k], ttw, ttw, k);
       } else {
 #pragma unroll
-        for (int k = 1; k < M; ++k) u[k] = twmul<+1>(u[k], twf, twfl, k * r);
+        for (int k = 1; k < M; ++k) u[k] = twmul<+1>(u[k], ttw, ttw + 1, 2 * k);
       }
       dft<M, +1>(u);
       cpx<T>* line = S + xi * sx + bl;
@@ -365,6 +503,10 @@ __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S) {
         if (j < m) line[j << bcl] = u[j];
     }
     __syncthreads();
+  }
+  if constexpr (BL) {
+    bl_inv_x<T, E, H, POT>(a, d, S, tab, xo, z, r, b0);
+    return;
   }
   // x-IFFT of the class's rows, written to the grid. Lane h of a line keeps
   // the same h for every row, so its slab lookups are loaded once.
@@ -508,8 +650,8 @@ __device__ __forceinline__ void fwd_x_rows(const KArgs& a, const cpx<T>* __restr
 // Class-parallel forward task (plane z, chunk, class r): x transform of the
 // class rows, y transform of length m per (slab, band) line, then the class
 // partial Z_r[xi][j] = w_ny^{-j*r} * Y[xi][j] stored as Z[z][xi][j][r][band].
-template <typename T, int E, int H, bool MF>
-__device__ void k2r_fwd_cls_task(const KArgs& a, int t, cpx<T>* S) {
+template <typename T, int E, int H, bool MF, bool BL>
+__device__ void k2r_fwd_cls_task(const KArgs& a, int t, cpx<T>* S, const TwEntry<T>* tab, int* xo) {
   const int s = find_sphere_k2r(a, t);
   const SphereDesc d = a.sph[s];
   const int lt = t - d.k2_start;
@@ -529,6 +671,50 @@ __device__ void k2r_fwd_cls_task(const KArgs& a, int t, cpx<T>* S) {
   cpx<T>* __restrict__ zp = reinterpret_cast<cpx<T>*>(a.col) + d.zp_off +
                             (static_cast<int64_t>(z) * nslab * ny + r) * nbp + b0;
 
+  if constexpr (BL) {
+    // the slab-line offsets of the x positions and the class twiddles
+    // w_ny^{-j*r}, j < m (FP32: hi and lo)
+    bl_stage_xoff(a, d, xo);
+    cpx<T>* ttw = reinterpret_cast<cpx<T>*>(reinterpret_cast<char*>(S) + a.lds_tab);
+    for (int j = threadIdx.x; j < m; j += blockDim.x) {
+      if constexpr (std::is_same<T, double>::value) {
+        ttw[j] = twf[j * r];
+      } else {
+        ttw[2 * j] = twf[j * r];
+        ttw[2 * j + 1] = twfl[j * r];
+      }
+    }
+    __syncthreads();
+    bl_fwd_x<T, E, H>(a, d, S, tab, xo, z, r, b0);
+    __syncthreads();
+    // y transform of length m per (slab, band) line; the class partials are
+    // written with streaming stores (the combine kernel reads them much later)
+    const __amdgpu_buffer_rsrc_t rz = buf_rsrc(zp);
+    const unsigned jstride = __builtin_amdgcn_readfirstlane(
+        static_cast<unsigned>(n1 * nbp) * static_cast<unsigned>(sizeof(cpx<T>)));
+    const int nlines = nslab << bcl;
+    for (int it = threadIdx.x; it < nlines; it += blockDim.x) {
+      const int bl = it & bmask, xi = it >> bcl;
+      const cpx<T>* line = S + xi * sx + bl;
+      cpx<T> u[kMaxRadixDev];
+#pragma unroll
+      for (int j = 0; j < kMaxRadixDev; ++j)
+        if (j < m) u[j] = line[j << bcl];
+      butterfly<-1>(m, u);
+      unsigned o = static_cast<unsigned>(xi * ny * nbp + bl) * static_cast<unsigned>(sizeof(cpx<T>));
+#pragma unroll
+      for (int j = 0; j < kMaxRadixDev; ++j) {
+        if (j < m) {
+          const cpx<T> val = std::is_same<T, double>::value ? twmul<-1>(u[j], ttw, ttw, j)
+                                                           : twmul<-1>(u[j], ttw, ttw + 1, 2 * j);
+          buf_store_nt(rz, val, o);
+          o += jstride;
+          asm volatile("" : "+v"(o));
+        }
+      }
+    }
+    return;
+  }
   fwd_x_rows<T, E, H, MF>(a, gin, xinv, S, r, z, b0, nb, 0, nslab);
   __syncthreads();
   const int nlines = nslab << bcl;
@@ -785,15 +971,29 @@ __global__ void __launch_bounds__(256) k1r_kernel(const KArgs a) {
 // forward so that neither variant's register allocation limits the other);
 // inverse tasks multiply by the real-space potential (compiled apart so that
 // the plain transform carries no potential registers)
-template <int S, typename T, int E, int H, bool MF, bool FC, int M>
+template <int S, typename T, int E, int H, bool MF, bool FC, int M, bool BL>
 __global__ void __launch_bounds__(512) k2r_kernel(const KArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
+  // band-inner lines: the x twiddles w_nx^{h*k} staged in LDS once per block,
+  // followed by the per-task table of slab-line offsets of the x positions
+  TwEntry<T>* tab = reinterpret_cast<TwEntry<T>*>(smem_raw + a.lds_twx);
+  int* xo = reinterpret_cast<int*>(smem_raw + a.lds_twx + (H > 1 ? E * H : 0) * sizeof(TwEntry<T>));
+  if constexpr (BL) {
+    if constexpr (H > 1)
+      bl_fill_twiddles<S, T>(tab, reinterpret_cast<const cpx<T>*>(a.rootx),
+                             reinterpret_cast<const cpx<T>*>(a.rootx_lo), E, H);
+    // the spare slab line: zeros for the x positions without a slab (inverse;
+    // no fold writes it), a sink for them (forward)
+    if constexpr (S > 0)
+      for (int i = threadIdx.x; i < a.sx; i += blockDim.x) lds[a.zline + i] = cpx<T>{0, 0};
+    __syncthreads();
+  }
   if (!a.persistent) {
     const int t = static_task_g(a.k2_tasks, a.g2);
     if (t >= 0) {
-      if constexpr (S > 0) k2r_inv_task<T, E, H, MF, M, FC>(a, t, lds);
-      else if constexpr (FC) k2r_fwd_cls_task<T, E, H, MF>(a, t, lds);
+      if constexpr (S > 0) k2r_inv_task<T, E, H, MF, M, FC, BL>(a, t, lds, tab, xo);
+      else if constexpr (FC) k2r_fwd_cls_task<T, E, H, MF, BL>(a, t, lds, tab, xo);
       else k2r_fwd_task<T, E, H, MF>(a, t, lds);
     }
     return;
@@ -805,8 +1005,8 @@ __global__ void __launch_bounds__(512) k2r_kernel(const KArgs a) {
     const int t = __builtin_amdgcn_readfirstlane(sh_task);
     __syncthreads();
     if (t < 0) break;
-    if constexpr (S > 0) k2r_inv_task<T, E, H, MF, M, FC>(a, t, lds);
-    else if constexpr (FC) k2r_fwd_cls_task<T, E, H, MF>(a, t, lds);
+    if constexpr (S > 0) k2r_inv_task<T, E, H, MF, M, FC, BL>(a, t, lds, tab, xo);
+    else if constexpr (FC) k2r_fwd_cls_task<T, E, H, MF, BL>(a, t, lds, tab, xo);
     else k2r_fwd_task<T, E, H, MF>(a, t, lds);
     __syncthreads();
   }
@@ -818,15 +1018,15 @@ __global__ void __launch_bounds__(512) k2r_kernel(const KArgs a) {
 // lines spread over 8 or 16 lanes (x lengths 32 .. 160) and m = 8 or 16.
 constexpr bool fold_m_compiled(int H, int m) { return (H == 8 || H == 16) && (m == 8 || m == 16); }
 
-template <int S, typename T, int E, int H, bool MF, bool FC, int M>
+template <int S, typename T, int E, int H, bool MF, bool FC, int M, bool BL = false>
 hipError_t launch_k2(const KArgs& a, int grid, int threads, size_t lds, hipStream_t st) {
-  hipLaunchKernelGGL((k2r_kernel<S, T, E, H, MF, FC, M>), dim3(grid), dim3(threads), lds, st, a);
+  hipLaunchKernelGGL((k2r_kernel<S, T, E, H, MF, FC, M, BL>), dim3(grid), dim3(threads), lds, st, a);
   return hipGetLastError();
 }
 
-template <int S, typename T, int E, int H, bool MF, bool FC, int M>
+template <int S, typename T, int E, int H, bool MF, bool FC, int M, bool BL = false>
 hipError_t attr_k2(size_t lds) {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(k2r_kernel<S, T, E, H, MF, FC, M>),
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(k2r_kernel<S, T, E, H, MF, FC, M, BL>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 

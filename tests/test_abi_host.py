@@ -157,15 +157,19 @@ def test_tiling_fits_lds():
 
 def test_default_tiling_c2():
     # the measured default for the 128^3, |G|<=32, 256-band complex128 shape:
-    # the inverse folds 8 classes of 16 (one workgroup per CU, so 512
+    # band-inner lines (path 3: one 128-byte piece of 8 bands per row of
+    # lanes); the inverse folds 8 classes of 16 (one workgroup per CU, so 512
     # threads), the forward writes partials of 16 classes of 8 (two
-    # workgroups per CU, 256 threads), register lines of 8 values over 16 lanes
+    # workgroups per CU, 256 threads)
     w = synth.make_workload("c2", nbands=1)
     p = host_plan(w.dims, [w.spheres[0].lin], nb=256, dtype="c128")
     inv, fwd = p.info["tuning"]["inv"], p.info["tuning"]["fwd"]
-    assert (inv["band_chunk"], inv["y_classes"], inv["threads"], inv["path"]) == (8, 8, 512, 2)
-    assert (fwd["band_chunk"], fwd["y_classes"], fwd["threads"], fwd["acc"]) == (8, 16, 256, 3)
-    assert inv["lanes"] == fwd["lanes"] == 16
+    assert (inv["band_chunk"], inv["y_classes"], inv["threads"], inv["path"]) == (8, 8, 512, 3)
+    assert (fwd["band_chunk"], fwd["y_classes"], fwd["threads"], fwd["acc"], fwd["path"]) == \
+        (8, 16, 256, 3, 3)
+    # the register path of lines over 16 lanes stays selectable
+    p = host_plan(w.dims, [w.spheres[0].lin], nb=256, dtype="c128", tuning=dict(path=2))
+    assert p.info["tuning"]["inv"]["path"] == 2 and p.info["tuning"]["inv"]["lanes"] == 16
     # an explicit thread count is kept
     p = host_plan(w.dims, [w.spheres[0].lin], nb=256, dtype="c128", tuning=dict(threads=256))
     assert p.info["tuning"]["inv"]["threads"] == 256
