@@ -276,15 +276,17 @@ size_t fold_table_bytes(const fftb_plan_s& P, int n1) {
   return ints * 4 + static_cast<size_t>(2 * n1 + 2 * (P.ny / n1)) * es_of(P.dtype);
 }
 
-// Band-inner shape of a line of length n: positions H = 4 (complex64) or 8
-// (complex128), so that one line fills a wavefront with one 128-byte piece of
-// bands per row of lanes.
+// Band-inner shape of a line of length n: H = 4 positions (complex64) or 8
+// (complex128), so that one line fills a wavefront; complex128 z lines may
+// also take 4 positions (two lines per wavefront, e.g. 180 = 45 x 4).
 bool bil_shape(int n, bool fp64, bool zaxis, int& E, int& H) {
-  const int h = fp64 ? 8 : 4;
-  if (n % h || !bil_shape_supported(fp64, zaxis, n / h, h)) return false;
-  E = n / h;
-  H = h;
-  return true;
+  for (int h : {fp64 ? 8 : 4, (fp64 && zaxis) ? 4 : 0}) {
+    if (!h || n % h || !bil_shape_supported(fp64, zaxis, n / h, h)) continue;
+    E = n / h;
+    H = h;
+    return true;
+  }
+  return false;
 }
 
 // Column slots of one plane of a sphere when its columns sit in zero-padded

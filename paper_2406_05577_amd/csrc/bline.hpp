@@ -88,7 +88,8 @@ __device__ __forceinline__ BLineCtx<E, H, S, T> bline_ctx(int h, const TwEntry<T
 
 // Radix-2 rounds across the positions: partner distance hs positions = BW*hs
 // lanes. Each lane fetches its partner's value through the LDS crossbar
-// (ds_bpermute: no LDS memory, no VALU moves), then the lower lane of a pair
+// (ds_bpermute: no LDS memory, no VALU moves; 8 lanes apart: a DPP row
+// rotation), then the lower lane of a pair
 // keeps own + partner, the upper one forms partner - own and multiplies it by
 // the round twiddle.
 template <int HS, int I, int E, int H, int S, typename T>
@@ -96,13 +97,23 @@ __device__ __forceinline__ void bl_rounds(cpx<T>* v, const BLineCtx<E, H, S, T>&
   if constexpr (HS >= 1) {
     constexpr int D = HS * band_width<T>();
     const T sg = c.sgn[I];
-    const int src = ((threadIdx.x & 63) ^ D) << 2;
-    // in groups of four values, so that the fetched values do not all stay live
+    if constexpr (D == 8) {
+      // partners 8 lanes apart sit in the same row of 16: a DPP row rotation
+      // (VALU moves; the LDS crossbar is left to the wider rounds)
 #pragma unroll
-    for (int k = 0; k < E; ++k) {
-      const T pr = lane_read(src, v[k].re), pi = lane_read(src, v[k].im);
-      v[k] = {ffma(sg, v[k].re, pr), ffma(sg, v[k].im, pi)};
-      if ((k & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+      for (int k = 0; k < E; ++k) {
+        const T pr = dpp_xor<8>(v[k].re), pi = dpp_xor<8>(v[k].im);
+        v[k] = {ffma(sg, v[k].re, pr), ffma(sg, v[k].im, pi)};
+      }
+    } else {
+      const int src = ((threadIdx.x & 63) ^ D) << 2;
+      // in groups of four values, so that the fetched values do not all stay live
+#pragma unroll
+      for (int k = 0; k < E; ++k) {
+        const T pr = lane_read(src, v[k].re), pi = lane_read(src, v[k].im);
+        v[k] = {ffma(sg, v[k].re, pr), ffma(sg, v[k].im, pi)};
+        if ((k & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+      }
     }
     if constexpr (HS > 1) {
       const cpx<T> w = c.rw[I];

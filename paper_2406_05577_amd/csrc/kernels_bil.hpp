@@ -122,7 +122,7 @@ __global__ void __launch_bounds__(256) k1b_kernel(const KArgs a) {
 // precision, for z lines (column kernel) and x lines (plane kernel).
 #define FFTB_BIL_Z_F32(X) X(8, 4) X(24, 4) X(32, 4) X(45, 4) X(64, 4)
 #define FFTB_BIL_X_F32(X) X(8, 4) X(24, 4) X(32, 4) X(36, 4)
-#define FFTB_BIL_Z_F64(X) X(4, 8) X(12, 8) X(16, 8) X(32, 8)
+#define FFTB_BIL_Z_F64(X) X(4, 8) X(12, 8) X(16, 8) X(32, 8) X(45, 4)
 #define FFTB_BIL_X_F64(X) X(4, 8) X(12, 8) X(16, 8) X(18, 8)
 
 template <int S, typename T, int E, int H>
