@@ -115,7 +115,16 @@ __device__ __forceinline__ void bl_rounds(cpx<T>* v, const BLineCtx<E, H, S, T>&
         if ((k & 3) == 3) __builtin_amdgcn_sched_barrier(0);
       }
     }
-    if constexpr (HS > 1) {
+    if constexpr (HS == 2) {
+      // the round twiddle is 1 or w_4 = S*i: a swap of the components with
+      // one sign, selected per lane
+      const bool rot = c.rw[I].im != static_cast<T>(0);
+#pragma unroll
+      for (int k = 0; k < E; ++k) {
+        const T re = v[k].re, im = v[k].im;
+        v[k] = {rot ? static_cast<T>(-S) * im : re, rot ? static_cast<T>(S) * re : im};
+      }
+    } else if constexpr (HS > 2) {
       const cpx<T> w = c.rw[I];
 #pragma unroll
       for (int k = 0; k < E; ++k) v[k] = cmul(v[k], w);

@@ -285,6 +285,45 @@ __device__ __forceinline__ void dft_ab(cpx<T>* v) {
   }
 }
 
+// R = A*B with A and B coprime: the prime-factor (Good-Thomas) split. The
+// input index n = (B*n1 + A*n2) mod R and the output index k = (B*(B^-1 mod A)*k1
+// + A*(A^-1 mod B)*k2) mod R turn the transform into A transforms of length B
+// and B of length A with no twiddles between them (Section 2.1 factorisation,
+// the index map of the Chinese remainder theorem).
+constexpr int inv_mod(int a, int m) {
+  for (int x = 1; x < m; ++x)
+    if ((a * x) % m == 1) return x;
+  return 1;
+}
+template <int A, int B, int S, typename T>
+__device__ __forceinline__ void dft_pfa(cpx<T>* v) {
+  constexpr int R = A * B;
+  cpx<T> u[R];
+  static_for<0, A>([&](auto i1) {
+    constexpr int n1 = decltype(i1)::value;
+    cpx<T> t[B];
+    static_for<0, B>([&](auto i2) {
+      constexpr int n2 = decltype(i2)::value;
+      t[n2] = v[(B * n1 + A * n2) % R];
+    });
+    dft<B, S>(t);
+#pragma unroll
+    for (int k2 = 0; k2 < B; ++k2) u[n1 * B + k2] = t[k2];
+  });
+  constexpr int cb = B * inv_mod(B % A, A), ca = A * inv_mod(A % B, B);
+  static_for<0, B>([&](auto j2) {
+    constexpr int k2 = decltype(j2)::value;
+    cpx<T> t[A];
+#pragma unroll
+    for (int n1 = 0; n1 < A; ++n1) t[n1] = u[n1 * B + k2];
+    dft<A, S>(t);
+    static_for<0, A>([&](auto j1) {
+      constexpr int k1 = decltype(j1)::value;
+      v[(cb * k1 + ca * k2) % R] = t[k1];
+    });
+  });
+}
+
 template <int R, int S, typename T>
 __device__ __forceinline__ void dft(cpx<T>* v) {
   if constexpr (R == 1) {
@@ -297,45 +336,45 @@ __device__ __forceinline__ void dft(cpx<T>* v) {
   } else if constexpr (R == 5) {
     dft5<S>(v);
   } else if constexpr (R == 6) {
-    dft_ab<3, 2, S>(v);
+    dft_pfa<2, 3, S>(v);
   } else if constexpr (R == 8) {
     dft_ab<4, 2, S>(v);
   } else if constexpr (R == 9) {
     dft_ab<3, 3, S>(v);
   } else if constexpr (R == 10) {
-    dft_ab<5, 2, S>(v);
+    dft_pfa<2, 5, S>(v);
   } else if constexpr (R == 12) {
-    dft_ab<4, 3, S>(v);
+    dft_pfa<4, 3, S>(v);
   } else if constexpr (R == 15) {
-    dft_ab<5, 3, S>(v);
+    dft_pfa<5, 3, S>(v);
   } else if constexpr (R == 16) {
     dft_ab<4, 4, S>(v);
   } else if constexpr (R == 18) {
-    dft_ab<6, 3, S>(v);
+    dft_pfa<2, 9, S>(v);
   } else if constexpr (R == 20) {
-    dft_ab<5, 4, S>(v);
+    dft_pfa<4, 5, S>(v);
   } else if constexpr (R == 24) {
-    dft_ab<8, 3, S>(v);
+    dft_pfa<8, 3, S>(v);
   } else if constexpr (R == 32) {
     dft_ab<8, 4, S>(v);
   } else if constexpr (R == 36) {
-    dft_ab<9, 4, S>(v);
+    dft_pfa<4, 9, S>(v);
   } else if constexpr (R == 40) {
-    dft_ab<8, 5, S>(v);
+    dft_pfa<8, 5, S>(v);
   } else if constexpr (R == 45) {
-    dft_ab<9, 5, S>(v);
+    dft_pfa<9, 5, S>(v);
   } else if constexpr (R == 48) {
-    dft_ab<16, 3, S>(v);
+    dft_pfa<16, 3, S>(v);
   } else if constexpr (R == 64) {
     dft_ab<8, 8, S>(v);
   } else if constexpr (R == 72) {
-    dft_ab<8, 9, S>(v);
+    dft_pfa<8, 9, S>(v);
   } else if constexpr (R == 96) {
-    dft_ab<16, 6, S>(v);
+    dft_pfa<32, 3, S>(v);
   } else if constexpr (R == 128) {
     dft_ab<16, 8, S>(v);
   } else if constexpr (R == 144) {
-    dft_ab<16, 9, S>(v);
+    dft_pfa<16, 9, S>(v);
   } else {
     static_assert(R == 1, "unsupported radix");
   }

@@ -818,7 +818,15 @@ __device__ __forceinline__ int find_sphere_k3r(const KArgs& a, int t) {
 }
 __device__ __forceinline__ bool codelet_radix(int R) {
   return R == 1 || R == 2 || R == 3 || R == 4 || R == 5 || R == 6 || R == 8 || R == 9 ||
-         R == 10 || R == 12 || R == 15 || R == 16;
+         R == 10 || R == 12 || R == 15 || R == 16 || R == 18 || R == 20;
+}
+// class counts of the combine: the codelets up to 20
+constexpr int kMaxCombine = 20;
+template <int S, typename T>
+__device__ __forceinline__ void combine_dft(int R, cpx<T>* v) {
+  if (R == 18) dft<18, S>(v);
+  else if (R == 20) dft<20, S>(v);
+  else butterfly<S>(R, v);
 }
 
 template <typename T>
@@ -851,8 +859,8 @@ __device__ void k3r_task(const KArgs& a, int t) {
     const __amdgpu_buffer_rsrc_t rz = buf_rsrc(zp);
     const __amdgpu_buffer_rsrc_t rc = buf_rsrc(colp);
     for (int it0 = threadIdx.x; it0 < items; it0 += NP * blockDim.x) {
-      cpx<T> u[NP][kMaxRadixDev];
-      int cs[NP][kMaxRadixDev];
+      cpx<T> u[NP][kMaxCombine];
+      int cs[NP][kMaxCombine];
       bool ok[NP];
       int bls[NP];
 #pragma unroll
@@ -869,7 +877,7 @@ __device__ void k3r_task(const KArgs& a, int t) {
         if (a.plane32) {
           const unsigned off = static_cast<unsigned>((xi * ny + j * n1) * nbp + bl) * es;
 #pragma unroll
-          for (int r = 0; r < kMaxRadixDev; ++r) {
+          for (int r = 0; r < kMaxCombine; ++r) {
             if (r < n1) {
               u[p][r] = buf_load(rz, zp, off, r * nbp_es);
               cs[p][r] = crow[r * m];
@@ -878,7 +886,7 @@ __device__ void k3r_task(const KArgs& a, int t) {
         } else {
           const cpx<T>* __restrict__ src = zp + (static_cast<int64_t>(xi) * ny + j * n1) * nbp + bl;
 #pragma unroll
-          for (int r = 0; r < kMaxRadixDev; ++r) {
+          for (int r = 0; r < kMaxCombine; ++r) {
             if (r < n1) {
               u[p][r] = src[r * nbp];
               cs[p][r] = crow[r * m];
@@ -889,15 +897,15 @@ __device__ void k3r_task(const KArgs& a, int t) {
 #pragma unroll
       for (int p = 0; p < NP; ++p) {
         if (!ok[p]) continue;
-        butterfly<-1>(n1, u[p]);
+        combine_dft<-1>(n1, u[p]);
         if (a.plane32) {
 #pragma unroll
-          for (int q = 0; q < kMaxRadixDev; ++q)
+          for (int q = 0; q < kMaxCombine; ++q)
             if (q < n1 && cs[p][q] >= 0)
               buf_store(rc, u[p][q], static_cast<unsigned>(cs[p][q] * nbp + bls[p]) * es, 0);
         } else {
 #pragma unroll
-          for (int q = 0; q < kMaxRadixDev; ++q)
+          for (int q = 0; q < kMaxCombine; ++q)
             if (q < n1 && cs[p][q] >= 0) colp[static_cast<int64_t>(cs[p][q]) * nbp + bls[p]] = u[p][q];
         }
       }
