@@ -85,12 +85,16 @@ __device__ void k1b_task(const KArgs& a, int t, const TwEntry<T>* tab) {
       }
     } else {
       const T sc = static_cast<T>(a.scale);
+      // the (column, z) lookups are all issued before the first store (the
+      // compiler does not move loads across the buffer stores, so a lookup
+      // per store would serialise their latencies)
+      int g[E];
 #pragma unroll
-      for (int k = 0; k < E; ++k) {
-        const int g = gidx[c * nz + k + E * q];
-        if (g >= 0 && bok)
-          buf_store(rsph, cscale(v[k], sc), static_cast<unsigned>(g * nb + b) * es, 0);
-      }
+      for (int k = 0; k < E; ++k) g[k] = gidx[c * nz + k + E * q];
+#pragma unroll
+      for (int k = 0; k < E; ++k)
+        if (g[k] >= 0 && bok)
+          buf_store(rsph, cscale(v[k], sc), static_cast<unsigned>(g[k] * nb + b) * es, 0);
     }
   }
 }
