@@ -99,12 +99,18 @@ typedef struct {
 
 /* Tiling of one direction. A zero field means "library default". */
 typedef struct {
-  int32_t band_chunk;   /* bands per workgroup tile, power of two, 1..64 */
+  int32_t band_chunk;   /* bands per workgroup tile, power of two, 1..64; path 3 takes one
+                           128-byte piece (16 complex64 / 8 complex128 bands), and for the
+                           complex64 inverse also half of one (8: the plane kernel's x lines
+                           over twice the positions, the column kernel on whole pieces) */
   int32_t y_classes;    /* n1: the plane kernel splits the y index into n1 residue classes; divides ny */
   int32_t x_rows;       /* rows per x-transform batch (LDS-stage path only) */
   int32_t col_tile;     /* columns per column-kernel task */
   int32_t threads;      /* plane-kernel workgroup size: 64, 128, 256 or 512 */
-  int32_t path;         /* 0 = choose, 1 = LDS-stage kernels, 2 = register-line kernels */
+  int32_t path;         /* 0 = choose, 1 = LDS-stage kernels, 2 = register-line kernels
+                           (bands across lanes, a line over 1..16 lanes), 3 = band-inner lines
+                           (one 128-byte piece of bands per row of 16 lanes, a line over the
+                           rows of a wavefront); UNSUPPORTED where no shape fits */
   int32_t acc;          /* forward only: 0 = choose, 1 = column accumulators in LDS (the plane's
                            columns split over workgroups), 2 = accumulators in global memory,
                            3 = one task per y class writing class partials that a combine

@@ -36,9 +36,10 @@ bool fold_m_supported(int H, int m);
 hipError_t launch_combine(const KArgs& a, bool fp64, int grid, int threads, hipStream_t st);
 hipError_t static_scratch_ptr(void** out);
 bool bil_shape_supported(bool fp64, bool zaxis, int E, int H);
+bool bil_narrow_supported(bool fp64, int E, int H);
 hipError_t launch_bil(int which, const KArgs& a, bool inverse, bool fp64, int E, int H, int grid,
                       int threads, size_t lds, hipStream_t st, int fold_m);
-hipError_t prepare_bil(bool fp64, int E, int H, size_t lds);
+hipError_t prepare_bil(bool fp64, int E, int H, size_t lds, bool narrow);
 hipError_t launch_zero_scratch(void* p, size_t bytes, hipStream_t st);
 }  // namespace fftb
 
@@ -84,6 +85,8 @@ struct DevBuf {
 // Tiling and task decomposition of one direction.
 struct DirCfg {
   int bc = 8, n1 = 1, m = 1, lx = 1, lc = 1, threads = 256;
+  int bc2 = 0;                      // plane kernel's band chunk when it differs (0 = bc)
+  bool narrow = false;              // band-inner inverse plane kernel on half pieces
   bool reg1 = false, reg2 = false;  // register path for the column / plane kernel
   bool mf1 = false, mf2 = false;    // DFT_16 stages on the matrix cores
   bool bil1 = false, bil2 = false;  // band-inner lines (column / plane kernel)
@@ -308,12 +311,13 @@ int64_t padded_slots(const SphereTables& s, int M) {
 
 // The band-inner kernels address every grid plane, column plane and class
 // partial plane with 32-bit offsets (below 2 GiB) and every sphere's
-// coefficients and column region below 4 GiB.
-bool bil_regions_fit(const fftb_plan_s& P, int bw) {
+// coefficients and column region below 4 GiB (columns in padded blocks of at
+// most M consecutive y).
+bool bil_regions_fit(const fftb_plan_s& P, int bw, int M = 16) {
   const int64_t es = es_of(P.dtype);
   for (const auto& sp : P.sph) {
     const int64_t nbp = band_stride(sp.nb, bw, es);
-    const int64_t colplane = padded_slots(sp, 16) * nbp * es;
+    const int64_t colplane = padded_slots(sp, M) * nbp * es;
     const int64_t zplane = static_cast<int64_t>(sp.nslab) * P.ny * nbp * es;
     const int64_t gplane = static_cast<int64_t>(P.nx) * P.ny * sp.nb * es;
     if (std::max(colplane, std::max(zplane, gplane)) >= (int64_t{1} << 31)) return false;
@@ -383,33 +387,49 @@ fftb_status choose_dir(fftb_plan_s& P, int d, const fftb_dir_tuning& t) {
   if (t.col_tile < 0) return fail(FFTB_ERR_INVALID, "col_tile must be >= 1");
   if (t.x_rows < 0) return fail(FFTB_ERR_INVALID, "x_rows must be >= 1");
   D.bc = bc;
+  D.bc2 = 0;
+  D.narrow = false;
   D.threads = threads;
   D.bil1 = D.bil2 = false;
   // ---- band-inner lines (path 3, and the default where the shapes exist):
-  // the band chunk is one 128-byte piece
+  // the band chunk is one 128-byte piece; the complex64 inverse plane kernel
+  // may take half of one (band_chunk = 8: x lines over twice the positions,
+  // the fold over classes of 16 or 32; the column kernel keeps whole pieces)
   const int bw = fp64 ? 8 : 16;
-  const bool bil_ok = (t.path == 0 || t.path == 3) && (t.band_chunk == 0 || t.band_chunk == bw) &&
-                      (t.lanes == 0) && !(P.flags & FFTB_PLAN_MFMA) && bil_regions_fit(P, bw);
+  const bool narrow = inverse && t.band_chunk == bw / 2;
+  const bool bil_ok = (t.path == 0 || t.path == 3) &&
+                      (t.band_chunk == 0 || t.band_chunk == bw || narrow) && (t.lanes == 0) &&
+                      !(P.flags & FFTB_PLAN_MFMA) && bil_regions_fit(P, bw);
   if (bil_ok) {
     int e1 = 0, h1 = 0, e2 = 0, h2 = 0;
     // the column kernel takes the band-inner shape of z, else a register shape
     const bool z_bil = bil_shape(P.nz, fp64, true, e1, h1);
     const bool z_ok = z_bil || reg_shape(P.nz, fp64, e1, h1, 0, true);
-    const bool x_ok = bil_shape(P.nx, fp64, false, e2, h2);
+    bool x_ok;
+    if (narrow) {
+      h2 = 8;
+      e2 = P.nx / h2;
+      x_ok = P.nx % h2 == 0 && bil_narrow_supported(fp64, e2, h2);
+    } else {
+      x_ok = bil_shape(P.nx, fp64, false, e2, h2);
+    }
+    const int bwp = narrow ? bw / 2 : bw;  // the plane kernel's band chunk
     if (z_ok && x_ok) {
       // inverse: the fewest classes whose slab fits (every class re-reads the
-      // plane's columns) with a register fold of length 8 or 16; forward: the
-      // fewest classes with a combine codelet, two workgroups per CU if possible
+      // plane's columns) with a register fold of length 8 or 16 (narrow: 16
+      // or 32); forward: the fewest classes with a combine codelet, two
+      // workgroups per CU if possible
       int best_n1 = 0, sx = 0, tab_at = 0, tw_at = 0;
       size_t best_b = 0;
       for (size_t cap : {(n1 || inverse) ? kLdsMax : kLdsMax / 2, kLdsMax}) {
         for (int c = 1; c <= P.ny && !best_n1; ++c) {
           if (P.ny % c || (n1 && c != n1)) continue;
           const int m = P.ny / c;
-          if (inverse ? !(m == 8 || m == 16) || !fold_slots_fit(P, m, bw)
+          const bool fold_ok = narrow ? (m == 16 || m == 32) : (m == 8 || m == 16);
+          if (inverse ? !fold_ok || !fold_slots_fit(P, m, bw) || !bil_regions_fit(P, bw, m)
                       : !single_codelet(m) || !combine_codelet(c))
             continue;
-          const size_t b = plane_lds_bil(P, c, bw, e2, h2, inverse, sx, tab_at, tw_at);
+          const size_t b = plane_lds_bil(P, c, bwp, e2, h2, inverse, sx, tab_at, tw_at);
           if (b > cap) continue;
           best_n1 = c;
           best_b = b;
@@ -417,8 +437,10 @@ fftb_status choose_dir(fftb_plan_s& P, int d, const fftb_dir_tuning& t) {
         if (best_n1) break;
       }
       if (best_n1) {
-        plane_lds_bil(P, best_n1, bw, e2, h2, inverse, sx, tab_at, tw_at);
+        plane_lds_bil(P, best_n1, bwp, e2, h2, inverse, sx, tab_at, tw_at);
         D.bc = bw;
+        D.bc2 = bwp;
+        D.narrow = narrow;
         D.bil1 = z_bil;
         D.bil2 = D.reg1 = D.reg2 = true;
         D.e1 = e1;
@@ -739,6 +761,7 @@ void build_slots(fftb_plan_s& P) {
 // Per-sphere descriptors and task ranges of one direction.
 void build_descs(fftb_plan_s& P, DirCfg& D) {
   const int bc = D.bc;
+  const int bc2 = D.bc2 ? D.bc2 : D.bc;  // plane kernel (band-inner: may be narrower)
   const int64_t N = static_cast<int64_t>(P.nx) * P.ny * P.nz;
   D.desc.clear();
   D.splits.clear();
@@ -762,12 +785,13 @@ void build_descs(fftb_plan_s& P, DirCfg& D) {
     d.nslab = s.nslab;
     d.nb = s.nb;
     d.nchunk = (s.nb + bc - 1) / bc;
+    d.nchunk2 = (s.nb + bc2 - 1) / bc2;
     d.nbp = static_cast<int32_t>(band_stride(s.nb, bc, es_of(P.dtype)));
     d.k1_start = k1;
     k1 += ((s.ncol + D.lc - 1) / D.lc) * d.nchunk;
     d.k1_end = k1;
     d.k2_start = k2;
-    k2 += P.nz * d.nchunk * (D.class_par ? D.n1 : D.nsplit);
+    k2 += P.nz * d.nchunk2 * (D.class_par ? D.n1 : D.nsplit);
     d.split_off = static_cast<int32_t>(D.splits.size());
     std::vector<int32_t> cuts;
     split_slabs(s, D.nsplit, cuts);
@@ -934,7 +958,8 @@ fftb_status device_setup(fftb_plan_s& P, hipStream_t st) {
     return fail(FFTB_ERR_HIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
   for (auto& D : P.dir) {
     if (!D.reg2) continue;
-    e = D.bil2 ? prepare_bil(fp64, D.e2, D.h2, r2) : prepare_reg(fp64, D.e2, D.h2, r2, D.mf2);
+    e = D.bil2 ? prepare_bil(fp64, D.e2, D.h2, r2, D.narrow)
+               : prepare_reg(fp64, D.e2, D.h2, r2, D.mf2);
     if (e != hipSuccess)
       return fail(FFTB_ERR_HIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
   }
@@ -953,6 +978,7 @@ KArgs make_args(const fftb_plan_s& P, const DirCfg& D, const void* in, void* out
   a.ny = P.ny;
   a.nz = P.nz;
   a.bcl = ilog2(D.bc);
+  a.bcl2 = ilog2(D.bc2 ? D.bc2 : D.bc);
   a.n1 = D.n1;
   a.m = D.m;
   a.lx = D.lx;
@@ -1090,7 +1116,8 @@ hipError_t enqueue(fftb_plan_s* P, const KArgs& a, const DirCfg& D, bool inverse
     if (which == 3) {
       e = launch_combine(a, fp64, g3, 256, st);
     } else if (which == 1 ? D.bil1 : D.bil2) {
-      e = launch_bil(which, a, inverse, fp64, which == 1 ? D.e1 : D.e2, which == 1 ? D.h1 : D.h2,
+      e = launch_bil(which == 2 && D.narrow ? 3 : which, a, inverse, fp64,
+                     which == 1 ? D.e1 : D.e2, which == 1 ? D.h1 : D.h2,
                      which == 1 ? g1 : g2, which == 1 ? 256 : D.threads, which == 1 ? 0 : D.lds2, st,
                      which == 1 ? 0 : D.fold_m);
     } else if (reg) {
@@ -1178,7 +1205,8 @@ void log_plan(const fftb_plan_s& P) {
                  "fold m %d\n",
                  d == 0 ? "inverse" : "forward", D.bc, D.n1, D.m, D.threads,
                  D.bil1 ? "band-inner" : D.reg1 ? "register" : "LDS-stage", D.e1, D.h1, D.lc, D.k1_tasks,
-                 D.bil2 ? "band-inner" : D.reg2 ? "register" : "LDS-stage", D.e2, D.h2, D.lds2, D.k2_tasks,
+                 D.narrow ? "band-inner, half pieces" : D.bil2 ? "band-inner" : D.reg2 ? "register" : "LDS-stage",
+                 D.e2, D.h2, D.lds2, D.k2_tasks,
                  D.fwd_cls ? ", class partials + combine" : "", D.mf2 || D.mf1 ? ", matrix-core DFT_16" : "",
                  D.fold_m);
   }
@@ -1271,7 +1299,7 @@ struct DirKey {
   bool operator==(const DirKey& o) const { return std::memcmp(v, o.v, sizeof v) == 0; }
 };
 DirKey dir_key(const DirCfg& D, bool inverse) {
-  DirKey k = {{D.bc, D.n1, D.threads,
+  DirKey k = {{D.narrow ? D.bc2 : D.bc, D.n1, D.threads,
                (D.reg1 ? 1 : 0) | (D.reg2 ? 2 : 0) | (D.bil1 ? 4 : 0) | (D.bil2 ? 8 : 0),
                D.reg2 ? D.h2 : D.lx,
                D.lc, inverse ? 0 : (D.fwd_cls ? 3 : D.acc_lds ? 1 : 2), D.nsplit, D.h1}};
@@ -1534,7 +1562,7 @@ fftb_status fftb_plan_create(fftb_plan* out, const int32_t dims[3], const fftb_s
     for (int d = 0; d < 2; ++d) {
       const DirCfg& D = P->dir[d];
       fftb_dir_tuning& o = d == 0 ? P->tun.inv : P->tun.fwd;
-      o.band_chunk = D.bc;
+      o.band_chunk = D.narrow ? D.bc2 : D.bc;
       o.y_classes = D.n1;
       o.x_rows = D.lx;
       o.col_tile = D.lc;

@@ -60,8 +60,9 @@ __device__ void bl_fill_twiddles(TwEntry<T>* tab, const cpx<T>* __restrict__ roo
   }
 }
 
-template <int E, int H, int S, typename T>
+template <int E, int H, int S, typename T, int BW = band_width<T>()>
 struct BLineCtx {
+  static constexpr int kBW = BW;  // bands per row of lanes
   static constexpr int kRounds = H > 1 ? log2_const<H>() : 1;
   const TwEntry<T>* tw;  // row h of the LDS table
   T sgn[kRounds];
@@ -69,9 +70,9 @@ struct BLineCtx {
 };
 
 // Context of the lane at position h of its line; tab is the LDS table.
-template <int E, int H, int S, typename T>
-__device__ __forceinline__ BLineCtx<E, H, S, T> bline_ctx(int h, const TwEntry<T>* tab) {
-  BLineCtx<E, H, S, T> c;
+template <int E, int H, int S, typename T, int BW = band_width<T>()>
+__device__ __forceinline__ BLineCtx<E, H, S, T, BW> bline_ctx(int h, const TwEntry<T>* tab) {
+  BLineCtx<E, H, S, T, BW> c;
   c.tw = tab + h * E;
   if constexpr (H > 1) {
     int i = 0;
@@ -92,17 +93,17 @@ __device__ __forceinline__ BLineCtx<E, H, S, T> bline_ctx(int h, const TwEntry<T
 // rotation), then the lower lane of a pair
 // keeps own + partner, the upper one forms partner - own and multiplies it by
 // the round twiddle.
-template <int HS, int I, int E, int H, int S, typename T>
-__device__ __forceinline__ void bl_rounds(cpx<T>* v, const BLineCtx<E, H, S, T>& c) {
+template <int HS, int I, int E, int H, int S, typename T, int BW>
+__device__ __forceinline__ void bl_rounds(cpx<T>* v, const BLineCtx<E, H, S, T, BW>& c) {
   if constexpr (HS >= 1) {
-    constexpr int D = HS * band_width<T>();
+    constexpr int D = HS * BW;
     const T sg = c.sgn[I];
-    if constexpr (D == 8) {
-      // partners 8 lanes apart sit in the same row of 16: a DPP row rotation
-      // (VALU moves; the LDS crossbar is left to the wider rounds)
+    if constexpr (D <= 8) {
+      // partners 4 or 8 lanes apart sit in the same row of 16: DPP moves
+      // (VALU; the LDS crossbar is left to the wider rounds)
 #pragma unroll
       for (int k = 0; k < E; ++k) {
-        const T pr = dpp_xor<8>(v[k].re), pi = dpp_xor<8>(v[k].im);
+        const T pr = dpp_xor<D>(v[k].re), pi = dpp_xor<D>(v[k].im);
         v[k] = {ffma(sg, v[k].re, pr), ffma(sg, v[k].im, pi)};
       }
     } else {
@@ -129,15 +130,15 @@ __device__ __forceinline__ void bl_rounds(cpx<T>* v, const BLineCtx<E, H, S, T>&
 #pragma unroll
       for (int k = 0; k < E; ++k) v[k] = cmul(v[k], w);
     }
-    bl_rounds<HS / 2, I + 1, E, H, S, T>(v, c);
+    bl_rounds<HS / 2, I + 1, E, H, S, T, BW>(v, c);
   }
 }
 
 // One band-inner line: on entry the lane at position h holds x[h + H*j] in
 // v[j] (j < E); on exit it holds X[k + E*bitrev(h)] in v[k]. Every lane of the
 // wavefront must take part (lanes of a line that has no data transform zeros).
-template <int E, int H, int S, typename T>
-__device__ __forceinline__ void bline_fft(cpx<T>* v, const BLineCtx<E, H, S, T>& c) {
+template <int E, int H, int S, typename T, int BW>
+__device__ __forceinline__ void bline_fft(cpx<T>* v, const BLineCtx<E, H, S, T, BW>& c) {
   dft<E, S>(v);
   if constexpr (H > 1) {
     // in groups of four: the scheduler would otherwise issue every table read
@@ -151,15 +152,15 @@ __device__ __forceinline__ void bline_fft(cpx<T>* v, const BLineCtx<E, H, S, T>&
         v[k] = cmul(v[k], cpx<double>{w.re, w.im});
       if ((k & 3) == 3) __builtin_amdgcn_sched_barrier(0);
     }
-    bl_rounds<H / 2, 0, E, H, S, T>(v, c);
+    bl_rounds<H / 2, 0, E, H, S, T, BW>(v, c);
   }
 }
 
 // Positions of a lane: band bl of the chunk, position h on its line, and the
 // line i of the wave (when one line uses only part of the wavefront).
-template <typename T, int H>
+template <typename T, int H, int BWL = band_width<T>()>
 struct BLane {
-  static constexpr int BW = band_width<T>();
+  static constexpr int BW = BWL;
   static constexpr int LPW = 64 / (BW * H);  // lines per wavefront
   int bl, h, sub;
   __device__ __forceinline__ BLane() {

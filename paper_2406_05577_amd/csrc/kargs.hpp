@@ -31,6 +31,7 @@ struct SphereDesc {
   int32_t nslab;
   int32_t nb;
   int32_t nchunk;      // ceil(nb / band_chunk)
+  int32_t nchunk2;     // the same for the band chunk of the plane kernel (band-inner lines)
   int32_t nbp;         // element stride between the band vectors of the column scratch and the
                        // class partials: nchunk*band_chunk, plus one 128-byte line when that
                        // is a multiple of 256 bytes (keeps strided runs off one L2 channel)
@@ -45,6 +46,7 @@ struct SphereDesc {
 struct KArgs {
   int nx, ny, nz;
   int bcl;           // log2(band chunk)
+  int bcl2;          // log2(band chunk) of the band-inner plane kernel (may be narrower)
   int n1, m;         // y residue classes and class length m = ny / n1
   int lx;            // rows per x batch in the plane kernel
   int lc;            // columns per column-kernel task

@@ -128,6 +128,10 @@ __global__ void __launch_bounds__(256) k1b_kernel(const KArgs a) {
 #define FFTB_BIL_X_F32(X) X(8, 4) X(24, 4) X(32, 4) X(36, 4)
 #define FFTB_BIL_Z_F64(X) X(4, 8) X(12, 8) X(16, 8) X(32, 8) X(45, 4)
 #define FFTB_BIL_X_F64(X) X(4, 8) X(12, 8) X(16, 8) X(18, 8)
+// narrow inverse x lines (complex64): half a 128-byte piece of bands (8) per
+// row of lanes, twice the positions. (The complex128 form, 4 bands over 16
+// positions, measured 1.5-1.9x slower than whole pieces and is not compiled.)
+#define FFTB_BIL_XN_F32(X) X(4, 8) X(12, 8) X(16, 8) X(18, 8)
 
 template <int S, typename T, int E, int H>
 hipError_t bil_launch_k1(const KArgs& a, int grid, int threads, hipStream_t st) {
@@ -163,11 +167,44 @@ hipError_t bil_plane(const KArgs& a, int grid, int threads, size_t lds, hipStrea
   }
 }
 
-// which: 1 = column kernel (shape of z), 2 = plane kernel (shape of x)
+// Narrow inverse plane kernel (complex64): fold of class length 16 or 32, with
+// or without the potential.
+template <typename T, int E, int H>
+hipError_t bil_plane_narrow(const KArgs& a, int grid, int threads, size_t lds, hipStream_t st,
+                            int fold_m, bool attr_only) {
+  constexpr int BWN = band_width<T>() / 2;
+  if (attr_only) {
+    hipError_t e = attr_k2<+1, T, E, H, false, false, 16, true, BWN>(lds);
+    if (e == hipSuccess) e = attr_k2<+1, T, E, H, false, true, 16, true, BWN>(lds);
+    if (e == hipSuccess) e = attr_k2<+1, T, E, H, false, false, 32, true, BWN>(lds);
+    if (e == hipSuccess) e = attr_k2<+1, T, E, H, false, true, 32, true, BWN>(lds);
+    return e;
+  }
+  const bool pot = a.pot != nullptr;
+  if (fold_m == 16)
+    return pot ? launch_k2<+1, T, E, H, false, true, 16, true, BWN>(a, grid, threads, lds, st)
+               : launch_k2<+1, T, E, H, false, false, 16, true, BWN>(a, grid, threads, lds, st);
+  if (fold_m == 32)
+    return pot ? launch_k2<+1, T, E, H, false, true, 32, true, BWN>(a, grid, threads, lds, st)
+               : launch_k2<+1, T, E, H, false, false, 32, true, BWN>(a, grid, threads, lds, st);
+  return hipErrorInvalidValue;
+}
+
+// which: 1 = column kernel (shape of z), 2 = plane kernel (shape of x),
+// 3 = narrow inverse plane kernel (shape of x)
 template <int S, typename T>
 hipError_t bil_dispatch(int which, const KArgs& a, int E, int H, int grid, int threads, size_t lds,
                         hipStream_t st, int fold_m, bool attr_only) {
   constexpr bool f64 = std::is_same<T, double>::value;
+  if (which == 3) {
+    if constexpr (S > 0 && !f64) {
+#define FFTB_X(e, h) \
+  if (E == e && H == h) return bil_plane_narrow<T, e, h>(a, grid, threads, lds, st, fold_m, attr_only);
+      FFTB_BIL_XN_F32(FFTB_X)
+#undef FFTB_X
+    }
+    return attr_only ? hipSuccess : hipErrorInvalidValue;
+  }
   if (which == 1) {
     if (attr_only) return hipSuccess;
 #define FFTB_X(e, h) \

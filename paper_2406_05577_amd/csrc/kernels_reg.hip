@@ -11,7 +11,9 @@ FFTB_BIL_DECL(extern, -1, float)
 FFTB_BIL_DECL(extern, +1, double)
 FFTB_BIL_DECL(extern, -1, double)
 
-// Band-inner shapes: z lines (column kernel) or x lines (plane kernel).
+// Band-inner shapes: z lines (column kernel) or x lines (plane kernel); the
+// narrow x lines (half a piece of bands per row) of the complex64 inverse
+// plane kernel.
 bool bil_shape_supported(bool fp64, bool zaxis, int E, int H) {
 #define FFTB_CHK(e, h) if (E == e && H == h) return true;
   if (fp64) {
@@ -19,6 +21,13 @@ bool bil_shape_supported(bool fp64, bool zaxis, int E, int H) {
   } else {
     if (zaxis) { FFTB_BIL_Z_F32(FFTB_CHK) } else { FFTB_BIL_X_F32(FFTB_CHK) }
   }
+#undef FFTB_CHK
+  return false;
+}
+bool bil_narrow_supported(bool fp64, int E, int H) {
+  if (fp64) return false;
+#define FFTB_CHK(e, h) if (E == e && H == h) return true;
+  FFTB_BIL_XN_F32(FFTB_CHK)
 #undef FFTB_CHK
   return false;
 }
@@ -33,10 +42,14 @@ hipError_t launch_bil(int which, const KArgs& a, bool inverse, bool fp64, int E,
                  : bil_dispatch<-1, float>(which, a, E, H, grid, threads, lds, st, fold_m, false);
 }
 
-// Allow the band-inner plane kernels of an x shape `lds` bytes of dynamic LDS.
-hipError_t prepare_bil(bool fp64, int E, int H, size_t lds) {
+// Allow the band-inner plane kernels of an x shape `lds` bytes of dynamic LDS
+// (narrow: the narrow inverse kernels).
+hipError_t prepare_bil(bool fp64, int E, int H, size_t lds, bool narrow) {
   KArgs dummy{};
   hipError_t e;
+  if (narrow)
+    return fp64 ? bil_dispatch<+1, double>(3, dummy, E, H, 0, 0, lds, nullptr, 0, true)
+                : bil_dispatch<+1, float>(3, dummy, E, H, 0, 0, lds, nullptr, 0, true);
   if (fp64) {
     e = bil_dispatch<+1, double>(2, dummy, E, H, 0, 0, lds, nullptr, 0, true);
     return e != hipSuccess ? e : bil_dispatch<-1, double>(2, dummy, E, H, 0, 0, lds, nullptr, 0, true);

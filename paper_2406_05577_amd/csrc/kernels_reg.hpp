@@ -209,19 +209,19 @@ __device__ void k1r_task(const KArgs& a, int t) {
 // Inverse: the row's occupied x values come from the class slab S[xi][k2][bl]
 // in LDS (zero at the other x), the line is transformed, and the whole row is
 // written to plane z of the grid (times the potential with POT).
-template <typename T, int E, int H, bool POT>
+template <typename T, int E, int H, bool POT, int BW>
 __device__ __forceinline__ void bl_inv_x(const KArgs& a, const SphereDesc& d, const cpx<T>* S,
                                          const TwEntry<T>* tab, const int* xo, int z, int r,
                                          int b0) {
-  using Lane = BLane<T, H>;
+  using Lane = BLane<T, H, BW>;
   const Lane ln;
   // opaque lane position: the line context is formed per task instead of being
   // hoisted out of the persistent loop, where it would stay live across the fold
   int h = ln.h;
   asm volatile("" : "+v"(h));
   const int q = bitrev_bits(h, log2_const<H>());
-  const auto ctx = bline_ctx<E, H, +1, T>(h, tab);
-  const int nx = a.nx, ny = a.ny, nb = d.nb, n1 = a.n1, m = a.m, bcl = a.bcl;
+  const auto ctx = bline_ctx<E, H, +1, T, BW>(h, tab);
+  const int nx = a.nx, ny = a.ny, nb = d.nb, n1 = a.n1, m = a.m, bcl = a.bcl2;
   cpx<T>* __restrict__ gout = reinterpret_cast<cpx<T>*>(a.out) + d.grid_off;
   const __amdgpu_buffer_rsrc_t gplane = buf_rsrc(gout + static_cast<int64_t>(z) * ny * nx * nb);
   const unsigned xstride =
@@ -276,17 +276,17 @@ __device__ __forceinline__ void bl_inv_x(const KArgs& a, const SphereDesc& d, co
 // Forward: the row is read from plane z of the grid, transformed, and its
 // occupied x values are kept in the class slab S[xi][k2][bl] (the others land
 // in the spare line).
-template <typename T, int E, int H>
+template <typename T, int E, int H, int BW>
 __device__ __forceinline__ void bl_fwd_x(const KArgs& a, const SphereDesc& d, cpx<T>* S,
                                          const TwEntry<T>* tab, const int* xo, int z, int r,
                                          int b0) {
-  using Lane = BLane<T, H>;
+  using Lane = BLane<T, H, BW>;
   const Lane ln;
   int h = ln.h;
   asm volatile("" : "+v"(h));
   const int q = bitrev_bits(h, log2_const<H>());
-  const auto ctx = bline_ctx<E, H, -1, T>(h, tab);
-  const int nx = a.nx, ny = a.ny, nb = d.nb, n1 = a.n1, m = a.m, bcl = a.bcl;
+  const auto ctx = bline_ctx<E, H, -1, T, BW>(h, tab);
+  const int nx = a.nx, ny = a.ny, nb = d.nb, n1 = a.n1, m = a.m, bcl = a.bcl2;
   const cpx<T>* __restrict__ gin = reinterpret_cast<const cpx<T>*>(a.in) + d.grid_off;
   const __amdgpu_buffer_rsrc_t gplane = buf_rsrc(gin + static_cast<int64_t>(z) * ny * nx * nb);
   const unsigned hstride =
@@ -333,7 +333,7 @@ __device__ __forceinline__ void bl_stage_xoff(const KArgs& a, const SphereDesc& 
 // slots are laid out in zero-padded blocks of M consecutive y per slab; one
 // thread folds and transforms a whole (slab, band) line in registers.
 // M == 0: generic fold.
-template <typename T, int E, int H, bool MF, int M, bool POT, bool BL>
+template <typename T, int E, int H, bool MF, int M, bool POT, bool BL, int BWK>
 __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S, const TwEntry<T>* tab, int* xo) {
   constexpr int L = log2_const<H>();
   const int s = find_sphere_k2r(a, t);
@@ -342,8 +342,10 @@ __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S, const TwEntry<T>*
   const int n1 = a.n1, m = a.m;
   const int r = lt % n1;
   const int rest0 = lt / n1;
-  const int chunk = rest0 % d.nchunk, z = rest0 / d.nchunk;
-  const int bcl = a.bcl, bmask = (1 << bcl) - 1;
+  // band-inner plane tasks may take a narrower band chunk than the column kernel
+  const int nchunk = BL ? d.nchunk2 : d.nchunk;
+  const int chunk = rest0 % nchunk, z = rest0 / nchunk;
+  const int bcl = BL ? a.bcl2 : a.bcl, bmask = (1 << bcl) - 1;
   const int b0 = chunk << bcl;
   const int nx = a.nx, ny = a.ny, sx = a.sx;
   const int nb = d.nb, npcol = d.npcol, nslab = d.nslab;
@@ -400,8 +402,9 @@ __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S, const TwEntry<T>*
     }
     __syncthreads();
     // NBF blocks per round trip (their loads are all issued before the first
-    // is accumulated; two measured best: four cost registers and time)
-    constexpr int NBF = FFTB_FOLD_BLOCKS > 0 ? FFTB_FOLD_BLOCKS : 2;
+    // is accumulated; two measured best: four cost registers and time; one
+    // for blocks of 32)
+    constexpr int NBF = FFTB_FOLD_BLOCKS > 0 ? FFTB_FOLD_BLOCKS : (M > 16 ? 1 : 2);
     // the plane's column scratch as a buffer (the host keeps it below 2 GiB):
     // a block's M loads share one offset register
     const __amdgpu_buffer_rsrc_t rs = buf_rsrc(colp);
@@ -505,7 +508,7 @@ __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S, const TwEntry<T>*
     __syncthreads();
   }
   if constexpr (BL) {
-    bl_inv_x<T, E, H, POT>(a, d, S, tab, xo, z, r, b0);
+    bl_inv_x<T, E, H, POT, BWK>(a, d, S, tab, xo, z, r, b0);
     return;
   }
   // x-IFFT of the class's rows, written to the grid. Lane h of a line keeps
@@ -650,7 +653,7 @@ __device__ __forceinline__ void fwd_x_rows(const KArgs& a, const cpx<T>* __restr
 // Class-parallel forward task (plane z, chunk, class r): x transform of the
 // class rows, y transform of length m per (slab, band) line, then the class
 // partial Z_r[xi][j] = w_ny^{-j*r} * Y[xi][j] stored as Z[z][xi][j][r][band].
-template <typename T, int E, int H, bool MF, bool BL>
+template <typename T, int E, int H, bool MF, bool BL, int BWK>
 __device__ void k2r_fwd_cls_task(const KArgs& a, int t, cpx<T>* S, const TwEntry<T>* tab, int* xo) {
   const int s = find_sphere_k2r(a, t);
   const SphereDesc d = a.sph[s];
@@ -658,8 +661,9 @@ __device__ void k2r_fwd_cls_task(const KArgs& a, int t, cpx<T>* S, const TwEntry
   const int n1 = a.n1, m = a.m;
   const int r = lt % n1;
   const int rest0 = lt / n1;
-  const int chunk = rest0 % d.nchunk, z = rest0 / d.nchunk;
-  const int bcl = a.bcl, bmask = (1 << bcl) - 1;
+  const int nchunk = BL ? d.nchunk2 : d.nchunk;
+  const int chunk = rest0 % nchunk, z = rest0 / nchunk;
+  const int bcl = BL ? a.bcl2 : a.bcl, bmask = (1 << bcl) - 1;
   const int b0 = chunk << bcl;
   const int ny = a.ny, sx = a.sx;
   const int nb = d.nb, nslab = d.nslab;
@@ -685,7 +689,7 @@ __device__ void k2r_fwd_cls_task(const KArgs& a, int t, cpx<T>* S, const TwEntry
       }
     }
     __syncthreads();
-    bl_fwd_x<T, E, H>(a, d, S, tab, xo, z, r, b0);
+    bl_fwd_x<T, E, H, BWK>(a, d, S, tab, xo, z, r, b0);
     __syncthreads();
     // y transform of length m per (slab, band) line; the class partials are
     // written with streaming stores (the combine kernel reads them much later)
@@ -979,7 +983,10 @@ __global__ void __launch_bounds__(256) k1r_kernel(const KArgs a) {
 // forward so that neither variant's register allocation limits the other);
 // inverse tasks multiply by the real-space potential (compiled apart so that
 // the plain transform carries no potential registers)
-template <int S, typename T, int E, int H, bool MF, bool FC, int M, bool BL>
+// BWK: bands per row of lanes of the band-inner x lines (one 128-byte piece,
+// or half of one for the narrow inverse tiling)
+template <int S, typename T, int E, int H, bool MF, bool FC, int M, bool BL,
+          int BWK = band_width<T>()>
 __global__ void __launch_bounds__(512) k2r_kernel(const KArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
@@ -1000,8 +1007,8 @@ __global__ void __launch_bounds__(512) k2r_kernel(const KArgs a) {
   if (!a.persistent) {
     const int t = static_task_g(a.k2_tasks, a.g2);
     if (t >= 0) {
-      if constexpr (S > 0) k2r_inv_task<T, E, H, MF, M, FC, BL>(a, t, lds, tab, xo);
-      else if constexpr (FC) k2r_fwd_cls_task<T, E, H, MF, BL>(a, t, lds, tab, xo);
+      if constexpr (S > 0) k2r_inv_task<T, E, H, MF, M, FC, BL, BWK>(a, t, lds, tab, xo);
+      else if constexpr (FC) k2r_fwd_cls_task<T, E, H, MF, BL, BWK>(a, t, lds, tab, xo);
       else k2r_fwd_task<T, E, H, MF>(a, t, lds);
     }
     return;
@@ -1013,8 +1020,8 @@ __global__ void __launch_bounds__(512) k2r_kernel(const KArgs a) {
     const int t = __builtin_amdgcn_readfirstlane(sh_task);
     __syncthreads();
     if (t < 0) break;
-    if constexpr (S > 0) k2r_inv_task<T, E, H, MF, M, FC, BL>(a, t, lds, tab, xo);
-    else if constexpr (FC) k2r_fwd_cls_task<T, E, H, MF, BL>(a, t, lds, tab, xo);
+    if constexpr (S > 0) k2r_inv_task<T, E, H, MF, M, FC, BL, BWK>(a, t, lds, tab, xo);
+    else if constexpr (FC) k2r_fwd_cls_task<T, E, H, MF, BL, BWK>(a, t, lds, tab, xo);
     else k2r_fwd_task<T, E, H, MF>(a, t, lds);
     __syncthreads();
   }
@@ -1026,15 +1033,17 @@ __global__ void __launch_bounds__(512) k2r_kernel(const KArgs a) {
 // lines spread over 8 or 16 lanes (x lengths 32 .. 160) and m = 8 or 16.
 constexpr bool fold_m_compiled(int H, int m) { return (H == 8 || H == 16) && (m == 8 || m == 16); }
 
-template <int S, typename T, int E, int H, bool MF, bool FC, int M, bool BL = false>
+template <int S, typename T, int E, int H, bool MF, bool FC, int M, bool BL = false,
+          int BWK = band_width<T>()>
 hipError_t launch_k2(const KArgs& a, int grid, int threads, size_t lds, hipStream_t st) {
-  hipLaunchKernelGGL((k2r_kernel<S, T, E, H, MF, FC, M, BL>), dim3(grid), dim3(threads), lds, st, a);
+  hipLaunchKernelGGL((k2r_kernel<S, T, E, H, MF, FC, M, BL, BWK>), dim3(grid), dim3(threads), lds, st, a);
   return hipGetLastError();
 }
 
-template <int S, typename T, int E, int H, bool MF, bool FC, int M, bool BL = false>
+template <int S, typename T, int E, int H, bool MF, bool FC, int M, bool BL = false,
+          int BWK = band_width<T>()>
 hipError_t attr_k2(size_t lds) {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(k2r_kernel<S, T, E, H, MF, FC, M, BL>),
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(k2r_kernel<S, T, E, H, MF, FC, M, BL, BWK>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 

@@ -175,6 +175,29 @@ def test_default_tiling_c2():
     assert p.info["tuning"]["inv"]["threads"] == 256
 
 
+def test_half_piece_inverse_tiling():
+    # complex64 inverse band chunk of half a 128-byte piece: the band-inner
+    # plane kernel on 8 bands per row of lanes, folding classes of 32; the
+    # forward and the column kernel keep whole pieces. complex128 has no such
+    # form (4 bands per row measured slower): its half chunk takes the
+    # register-line path
+    w = synth.make_workload("c5", nbands=1)
+    lins = [s.lin for s in w.spheres]
+    p = host_plan(w.dims, lins, nb=128, dtype="c64", tuning=dict(inv_band_chunk=8))
+    inv, fwd = p.info["tuning"]["inv"], p.info["tuning"]["fwd"]
+    assert (inv["band_chunk"], inv["y_classes"], inv["path"]) == (8, 5, 3), inv
+    assert (fwd["band_chunk"], fwd["path"]) == (16, 3), fwd
+    p = host_plan(w.dims, lins, nb=128, dtype="c128", tuning=dict(inv_band_chunk=4))
+    assert p.info["tuning"]["inv"]["path"] != 3
+    # x lengths without a half-piece line shape fall back to another path
+    m2, lin2 = synth.sphere_map((30, 24, 36), (7, 6, 8))
+    p = host_plan((30, 24, 36), [lin2], nb=8, dtype="c64", tuning=dict(inv_band_chunk=8))
+    assert p.info["tuning"]["inv"]["path"] != 3
+    _expect_status(pk.FFTB_ERR_UNSUPPORTED,
+                   lambda: host_plan((30, 24, 36), [lin2], nb=8, dtype="c64",
+                                     tuning=dict(inv_band_chunk=8, path=3)))
+
+
 def test_mfma_flag_validation():
     m, lin = synth.sphere_map((128, 16, 128), (20, 4, 20))
     p = pk.Plan((128, 16, 128), [lin], 16, dtype="c64", flags=pk.PLAN_HOST_ONLY | pk.PLAN_MFMA)

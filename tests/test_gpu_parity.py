@@ -70,6 +70,43 @@ def test_register_path(case, ti, dtype):
     assert max(e) <= TOL[dtype], (t, e)
 
 
+@pytest.mark.parametrize("flags", [0, 5])
+@pytest.mark.parametrize("case", range(len(REG_CASES)))
+def test_band_inner_half_pieces(case, flags):
+    """Band-inner lines with the complex64 inverse plane kernel on half a
+    128-byte piece of bands per row of lanes (8 bands; x lines over 8
+    positions, the fold over classes of 16 or 32), ragged band counts, plain
+    and persistent + graph replays; then the fused potential step."""
+    import oracle
+    import torch
+    from gpu_util import make_plan, to_device, split_sphere
+    dtype = "c64"
+    dims, semi, kpts, nb, seed = REG_CASES[case]
+    w = synth.small_workload(dims, semi, kpts, nb + 5, seed=seed, shuffle=True)
+    half = 8
+    tun = dict(path=3, inv_band_chunk=half)
+    p = make_plan(w, dtype=dtype, flags=flags, tuning=tun)
+    inv = p.info["tuning"]["inv"]
+    assert inv["path"] == 3 and inv["band_chunk"] == half, inv
+    assert p.info["tuning"]["fwd"]["band_chunk"] == 2 * half
+    p.close()
+    e = check_workload(w, dtype, flags=flags, tuning=tun, reps=2)
+    print(dims, dtype, flags, inv, e)
+    assert max(e) <= TOL[dtype], e
+    # the potential-weighted variant of the same kernel
+    npdt, rdt = np.complex64, np.float32
+    v = np.random.default_rng(78).standard_normal(dims[::-1]).astype(rdt)
+    coeffs = [c.astype(npdt) for c in w.coeffs]
+    p = make_plan(w, dtype=dtype, flags=flags, tuning=tun)
+    sph = to_device(np.concatenate([c.reshape(-1) for c in coeffs]), dtype)
+    out = p.apply_potential(sph, torch.from_numpy(v.reshape(-1)).to("cuda"))
+    torch.cuda.synchronize()
+    for s, c, o in zip(w.spheres, coeffs, split_sphere(w, out.cpu().numpy())):
+        ref = oracle.apply_potential(dims, s.lin, c.astype(np.complex128), v.astype(np.float64))
+        assert rel(o, ref) <= TOL[dtype], (rel(o, ref), dtype, flags)
+    p.close()
+
+
 TUNINGS = [
     dict(band_chunk=1), dict(band_chunk=2, threads=64), dict(band_chunk=4, col_tile=3),
     dict(band_chunk=16, threads=128), dict(y_classes=2, x_rows=1), dict(y_classes=5, x_rows=2),
