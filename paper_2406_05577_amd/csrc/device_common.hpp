@@ -83,6 +83,15 @@ __device__ __forceinline__ cpx<float> buf_load(__amdgpu_buffer_rsrc_t r, const c
   return __builtin_bit_cast(cpx<float>, x);
 }
 
+// two adjacent complex64 values in one 16-byte load
+__device__ __forceinline__ void buf_load2(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff,
+                                          cpx<float>& a, cpx<float>& b) {
+  typedef float v4f __attribute__((ext_vector_type(4)));
+  const v4f x = __builtin_bit_cast(v4f, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+  a = {x.x, x.y};
+  b = {x.z, x.w};
+}
+
 __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, cpx<double> v, unsigned voff,
                                           unsigned soff) {
   typedef int v4i __attribute__((ext_vector_type(4)));

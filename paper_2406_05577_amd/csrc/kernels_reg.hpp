@@ -404,32 +404,44 @@ __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S, const TwEntry<T>*
     // NBF blocks per round trip (their loads are all issued before the first
     // is accumulated; two measured best: four cost registers and time; one
     // for blocks of 32)
-    constexpr int NBF = FFTB_FOLD_BLOCKS > 0 ? FFTB_FOLD_BLOCKS : (M > 16 ? 1 : 2);
+    constexpr int NBF = FFTB_FOLD_BLOCKS > 0
+                            ? FFTB_FOLD_BLOCKS
+                            : ((M > 16 || (BL && std::is_same<T, float>::value)) ? 1 : 2);
+    static_assert(NBF >= 1, "fold blocks per round trip");
     // the plane's column scratch as a buffer (the host keeps it below 2 GiB):
     // a block's M loads share one offset register
     const __amdgpu_buffer_rsrc_t rs = buf_rsrc(colp);
     const unsigned slot_bytes =
         __builtin_amdgcn_readfirstlane(static_cast<unsigned>(nbp) * sizeof(cpx<T>));
-    const int nlines = nslab << bcl;
+    // FB bands per lane: complex64 band-inner folds of blocks up to 16 take two
+    // adjacent bands per lane (one 16-byte load each), halving the load
+    // instructions
+    constexpr int FB = (BL && std::is_same<T, float>::value && M <= 16) ? 2 : 1;
+    constexpr int FBL = FB == 2 ? 1 : 0;
+    const int nlines = nslab << (bcl - FBL);
     for (int it = threadIdx.x; it < nlines; it += blockDim.x) {
-      const int bl = it & bmask;
-      const int xi = tord[it >> bcl];
+      const int bl = (it & (bmask >> FBL)) << FBL;
+      const int xi = tord[it >> (bcl - FBL)];
       const int nh = tn[xi];
       const int32_t* lst = tl + xi * n1;
-      cpx<T> u[M];
+      cpx<T> u[FB][M];
 #pragma unroll
-      for (int k = 0; k < M; ++k) u[k] = cpx<T>{0, 0};
-      auto accumulate = [&](const cpx<T>* v, int tb, bool use) {
+      for (int f = 0; f < FB; ++f)
+#pragma unroll
+        for (int k = 0; k < M; ++k) u[f][k] = cpx<T>{0, 0};
+      auto accumulate = [&](const cpx<T> (*v)[M], int tb, bool use) {
         cpx<T> w = troot[2 * tb];
         if (!use) w = cpx<T>{0, 0};
         if constexpr (std::is_same<T, float>::value) {
           cpx<T> wl = troot[2 * tb + 1];
           if (!use) wl = cpx<T>{0, 0};
 #pragma unroll
-          for (int k = 0; k < M; ++k) u[k] = cmac_hl(u[k], v[k], w, wl);
+          for (int f = 0; f < FB; ++f)
+#pragma unroll
+            for (int k = 0; k < M; ++k) u[f][k] = cmac_hl(u[f][k], v[f][k], w, wl);
         } else {
 #pragma unroll
-          for (int k = 0; k < M; ++k) u[k] = cmac(u[k], v[k], w);
+          for (int k = 0; k < M; ++k) u[0][k] = cmac(u[0][k], v[0][k], w);
         }
       };
       auto off_of = [&](int e) {
@@ -439,28 +451,43 @@ __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S, const TwEntry<T>*
         // past the list's end the last block is loaded again (cache hits) and
         // accumulated with weight zero
         int eb[NBF];
-        cpx<T> vb[NBF][M];
+        cpx<T> vb[NBF][FB][M];
 #pragma unroll
         for (int b = 0; b < NBF; ++b) {
           eb[b] = lst[min(i + b, nh - 1)];
           const unsigned o = off_of(eb[b]);
 #pragma unroll
-          for (int k = 0; k < M; ++k) vb[b][k] = buf_load(rs, colp, o, k * slot_bytes);
+          for (int k = 0; k < M; ++k) {
+            if constexpr (FB == 2)
+              buf_load2(rs, o, k * slot_bytes, vb[b][0][k], vb[b][1][k]);
+            else
+              vb[b][0][k] = buf_load(rs, colp, o, k * slot_bytes);
+          }
         }
 #pragma unroll
         for (int b = 0; b < NBF; ++b) accumulate(vb[b], eb[b] & 1023, i + b < nh);
       }
-      if constexpr (std::is_same<T, double>::value) {
-#pragma unroll
-        for (int k = 1; k < M; ++k) u[k] = twmul<+1>(u[k], ttw, ttw, k);
-      } else {
-#pragma unroll
-        for (int k = 1; k < M; ++k) u[k] = twmul<+1>(u[k], ttw, ttw + 1, 2 * k);
-      }
-      dft<M, +1>(u);
       cpx<T>* line = S + xi * sx + bl;
 #pragma unroll
-      for (int k = 0; k < M; ++k) line[k << bcl] = u[k];
+      for (int f = 0; f < FB; ++f) {
+        if constexpr (std::is_same<T, double>::value) {
+#pragma unroll
+          for (int k = 1; k < M; ++k) u[f][k] = twmul<+1>(u[f][k], ttw, ttw, k);
+        } else {
+#pragma unroll
+          for (int k = 1; k < M; ++k) u[f][k] = twmul<+1>(u[f][k], ttw, ttw + 1, 2 * k);
+        }
+        dft<M, +1>(u[f]);
+      }
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        if constexpr (FB == 2) {
+          typedef float v4f __attribute__((ext_vector_type(4)));
+          *reinterpret_cast<v4f*>(line + (k << bcl)) = v4f{u[0][k].re, u[0][k].im, u[1][k].re, u[1][k].im};
+        } else {
+          line[k << bcl] = u[0][k];
+        }
+      }
     }
     __syncthreads();
   } else {
