@@ -106,6 +106,7 @@ def kernel_id(name: str):
     the direction: 1 = inverse, -1 = forward)."""
     n = name.replace(" ", "")
     for tag, inv, fwd in (("k1r_kernel<", "column_inverse", "column_forward"),
+                          ("k1b_kernel<", "column_inverse", "column_forward"),
                           ("k1_kernel<", "column_inverse", "column_forward"),
                           ("k2r_kernel<", "plane_inverse", "plane_forward"),
                           ("k2_kernel<", "plane_inverse", "plane_forward")):
