@@ -285,22 +285,27 @@ class Form:
                               torch.empty_like(sph)))
         self.nsets = nsets
         self.i = 0
+        self.used = set()   # buffer sets a step has run on
 
     def step(self):
         sph, grid, back = self.sets[self.i]
+        self.used.add(self.i)
         self.i = (self.i + 1) % self.nsets
         self.plan.sphere_to_grid(sph, grid)
         self.plan.grid_to_sphere(grid, back)
 
     def step_potential(self, vpot):
         sph, grid, back = self.sets[self.i]
+        self.used.add(self.i)
         self.i = (self.i + 1) % self.nsets
         self.plan.apply_potential(sph, vpot, grid=grid, out=back)
 
     def rt_error(self):
+        """Relative round-trip error, worst over the buffer sets that ran."""
         import numpy as np
         errs = []
-        for sph, _, back in self.sets:
+        for i in sorted(self.used):
+            sph, _, back = self.sets[i]
             ref = sph.cpu().numpy()
             errs.append(float(np.linalg.norm(back.cpu().numpy() - ref) / np.linalg.norm(ref)))
         return max(errs)
