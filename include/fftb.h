@@ -111,11 +111,13 @@ typedef struct {
                            (bands across lanes, a line over 1..16 lanes), 3 = band-inner lines
                            (one 128-byte piece of bands per row of 16 lanes, a line over the
                            rows of a wavefront); UNSUPPORTED where no shape fits */
-  int32_t acc;          /* forward only: 0 = choose, 1 = column accumulators in LDS (the plane's
+  int32_t acc;          /* forward: 0 = choose, 1 = column accumulators in LDS (the plane's
                            columns split over workgroups), 2 = accumulators in global memory,
                            3 = one task per y class writing class partials that a combine
                            kernel turns into columns (a length-n1 DFT over the classes;
-                           one split) */
+                           one split). inverse, path 3: 0 = choose, 1 = one y class per plane
+                           task, 2 = two classes r and r + n1/2 per task, folded from the same
+                           reads of the plane's columns (even n1, classes of 16) */
   int32_t splits;       /* forward only: column splits per (plane, chunk), 1..8 */
   int32_t lanes;        /* register path: lanes per transform line (x lines of the plane
                            kernel, z lines of the column kernel): 0 = choose, or 1, 4, 8, 16

@@ -87,6 +87,9 @@ struct DirCfg {
   int bc = 8, n1 = 1, m = 1, lx = 1, lc = 1, threads = 256;
   int bc2 = 0;                      // plane kernel's band chunk when it differs (0 = bc)
   bool narrow = false;              // band-inner inverse plane kernel on half pieces
+  int qc = 1;                       // inverse band-inner: y classes per plane task (2: pairs)
+  int ovf_lines = 0;                // class pairs: lines per task held in the overflow scratch
+  int64_t ovf_off = 0;              // class pairs: overflow scratch offset in the column region
   bool reg1 = false, reg2 = false;  // register path for the column / plane kernel
   bool mf1 = false, mf2 = false;    // DFT_16 stages on the matrix cores
   bool bil1 = false, bil2 = false;  // band-inner lines (column / plane kernel)
@@ -275,10 +278,11 @@ bool fold_slots_fit(const fftb_plan_s& P, int M, int bc) {
 // LDS of the inverse fold's staged tables: per slab n1 block entries, a count
 // and the slab order, then n1 roots (hi and lo) of the class and its m
 // twiddles (FP32: hi and lo).
-size_t fold_table_bytes(const fftb_plan_s& P, int n1) {
+size_t fold_table_bytes(const fftb_plan_s& P, int n1, bool pair = false) {
   const size_t ints = ((static_cast<size_t>(P.max_nslab) * n1 + 3) & ~size_t{3}) +
                       2 * ((P.max_nslab + 3) & ~3);
-  return ints * 4 + static_cast<size_t>(2 * n1 + 2 * (P.ny / n1)) * es_of(P.dtype);
+  // class pairs: the second class's twiddles too
+  return ints * 4 + static_cast<size_t>(2 * n1 + (pair ? 4 : 2) * (P.ny / n1)) * es_of(P.dtype);
 }
 
 // Band-inner shape of a line of length n: H = 4 positions (complex64) or 8
@@ -330,14 +334,14 @@ bool bil_regions_fit(const fftb_plan_s& P, int bw, int M = 16) {
 // (max_nslab lines of m x bw values, plus the spare line), then (inverse) the
 // fold tables, then the E x H twiddle table of the x lines.
 size_t plane_lds_bil(const fftb_plan_s& P, int n1, int bw, int e2, int h2, bool inverse,
-                     int& sx, int& tab_at, int& tw_at) {
+                     int& sx, int& tab_at, int& tw_at, bool pair = false) {
   const int m = P.ny / n1;
   sx = m * bw;
   size_t b = static_cast<size_t>(P.max_nslab + 1) * sx * es_of(P.dtype);
   b = (b + 15) & ~size_t{15};
   tab_at = static_cast<int>(b);
   // inverse: the fold tables; forward: the class twiddles (FP32 hi and lo)
-  if (inverse) b = (b + fold_table_bytes(P, n1) + 15) & ~size_t{15};
+  if (inverse) b = (b + fold_table_bytes(P, n1, pair) + 15) & ~size_t{15};
   else b = (b + static_cast<size_t>(2 * m) * es_of(P.dtype) + 15) & ~size_t{15};
   tw_at = static_cast<int>(b);
   // the twiddle table (lines of more than one position), then the slab-line
@@ -389,6 +393,7 @@ fftb_status choose_dir(fftb_plan_s& P, int d, const fftb_dir_tuning& t) {
   D.bc = bc;
   D.bc2 = 0;
   D.narrow = false;
+  D.qc = 1;
   D.threads = threads;
   D.bil1 = D.bil2 = false;
   // ---- band-inner lines (path 3, and the default where the shapes exist):
@@ -437,7 +442,18 @@ fftb_status choose_dir(fftb_plan_s& P, int d, const fftb_dir_tuning& t) {
         if (best_n1) break;
       }
       if (best_n1) {
-        plane_lds_bil(P, best_n1, bwp, e2, h2, inverse, sx, tab_at, tw_at);
+        // inverse class pairs (r, r + n1/2 per task: one read of the plane's
+        // columns serves both) where the fold has length 16 and the second
+        // class's twiddles fit
+        bool pair = false;
+        if (inverse && !narrow && t.acc != 1 && best_n1 % 2 == 0 && P.ny / best_n1 == 16) {
+          int sx2 = 0, tab2 = 0, tw2 = 0;
+          pair = plane_lds_bil(P, best_n1, bwp, e2, h2, true, sx2, tab2, tw2, true) <= kLdsMax;
+        }
+        if (inverse && t.acc == 2 && !pair)
+          return fail(FFTB_ERR_UNSUPPORTED, "class pairs need an even class count with classes of 16");
+        best_b = plane_lds_bil(P, best_n1, bwp, e2, h2, inverse, sx, tab_at, tw_at, pair);
+        D.qc = pair ? 2 : 1;
         D.bc = bw;
         D.bc2 = bwp;
         D.narrow = narrow;
@@ -791,7 +807,7 @@ void build_descs(fftb_plan_s& P, DirCfg& D) {
     k1 += ((s.ncol + D.lc - 1) / D.lc) * d.nchunk;
     d.k1_end = k1;
     d.k2_start = k2;
-    k2 += P.nz * d.nchunk2 * (D.class_par ? D.n1 : D.nsplit);
+    k2 += P.nz * d.nchunk2 * (D.class_par ? D.n1 / D.qc : D.nsplit);
     d.split_off = static_cast<int32_t>(D.splits.size());
     std::vector<int32_t> cuts;
     split_slabs(s, D.nsplit, cuts);
@@ -819,6 +835,17 @@ void build_descs(fftb_plan_s& P, DirCfg& D) {
   D.k2_tasks = k2;
   D.k3_tasks = k3;
   D.col_elems = coff + zoff;
+  // inverse class pairs: (slab, band) lines past the kPairRegLines per
+  // thread whose second class waits in registers keep it in an overflow
+  // region, m values per line, one region per plane task
+  D.ovf_lines = 0;
+  D.ovf_off = 0;
+  if (D.qc == 2) {
+    for (auto& s : P.sph)
+      D.ovf_lines = std::max(D.ovf_lines, s.nslab * bc2 - kPairRegLines * D.threads);
+    D.ovf_off = D.col_elems;
+    D.col_elems += static_cast<int64_t>(k2) * D.m * D.ovf_lines;
+  }
 }
 
 fftb_status dev_alloc(fftb_plan_s& P, size_t bytes, void** out) {
@@ -996,7 +1023,10 @@ KArgs make_args(const fftb_plan_s& P, const DirCfg& D, const void* in, void* out
   a.sx = D.sx;
   a.nsplit = D.nsplit;
   a.fwd_cls = D.fwd_cls ? 1 : 0;
-  a.g2 = D.reg2 ? (D.class_par ? D.n1 : D.nsplit) : 1;
+  a.g2 = D.reg2 ? (D.class_par ? D.n1 / D.qc : D.nsplit) : 1;
+  a.qc = D.qc;
+  a.ovf_lines = D.ovf_lines;
+  a.ovf_off = D.ovf_off;
   // 32-bit buffer addressing where every region it covers allows it
   a.plane32 = 1;
   a.k1buf = 1;
@@ -1057,7 +1087,7 @@ int occupancy(size_t lds) {
 // Static grids cover every task under the group-interleaved XCD mapping:
 // ceil(groups / 8) groups per XCD.
 void grids(const fftb_plan_s& P, const DirCfg& D, int& g1, int& g2, int& g3) {
-  const int G = D.reg2 ? (D.class_par ? D.n1 : D.nsplit) : 1;
+  const int G = D.reg2 ? (D.class_par ? D.n1 / D.qc : D.nsplit) : 1;
   g1 = ((D.k1_tasks + 7) / 8) * 8;
   g2 = ((D.k2_tasks / G + 7) / 8) * 8 * G;
   g3 = ((D.k3_tasks + 7) / 8) * 8;
@@ -1207,7 +1237,8 @@ void log_plan(const fftb_plan_s& P) {
                  D.bil1 ? "band-inner" : D.reg1 ? "register" : "LDS-stage", D.e1, D.h1, D.lc, D.k1_tasks,
                  D.narrow ? "band-inner, half pieces" : D.bil2 ? "band-inner" : D.reg2 ? "register" : "LDS-stage",
                  D.e2, D.h2, D.lds2, D.k2_tasks,
-                 D.fwd_cls ? ", class partials + combine" : "", D.mf2 || D.mf1 ? ", matrix-core DFT_16" : "",
+                 D.fwd_cls ? ", class partials + combine" : D.qc == 2 ? ", class pairs" : "",
+                 D.mf2 || D.mf1 ? ", matrix-core DFT_16" : "",
                  D.fold_m);
   }
 }
@@ -1302,7 +1333,7 @@ DirKey dir_key(const DirCfg& D, bool inverse) {
   DirKey k = {{D.narrow ? D.bc2 : D.bc, D.n1, D.threads,
                (D.reg1 ? 1 : 0) | (D.reg2 ? 2 : 0) | (D.bil1 ? 4 : 0) | (D.bil2 ? 8 : 0),
                D.reg2 ? D.h2 : D.lx,
-               D.lc, inverse ? 0 : (D.fwd_cls ? 3 : D.acc_lds ? 1 : 2), D.nsplit, D.h1}};
+               D.lc, inverse ? D.qc : (D.fwd_cls ? 3 : D.acc_lds ? 1 : 2), D.nsplit, D.h1}};
   return k;
 }
 
@@ -1568,7 +1599,8 @@ fftb_status fftb_plan_create(fftb_plan* out, const int32_t dims[3], const fftb_s
       o.col_tile = D.lc;
       o.threads = D.threads;
       o.path = D.bil2 ? 3 : (D.reg1 && D.reg2) ? 2 : (D.reg1 || D.reg2) ? 0 : 1;
-      o.acc = d == 0 ? 0 : D.fwd_cls ? 3 : (D.reg2 && D.acc_lds) ? 1 : 2;
+      o.acc = d == 0 ? ((D.bil2 && !D.narrow) ? D.qc : 0)
+                     : D.fwd_cls ? 3 : (D.reg2 && D.acc_lds) ? 1 : 2;
       o.splits = D.nsplit;
       o.lanes = D.bil2 ? 0 : D.reg2 ? D.h2 : (D.reg1 ? D.h1 : 0);
     }

@@ -7,6 +7,10 @@ namespace fftb {
 
 constexpr int kAxisStages = 8;
 
+// Inverse class pairs: (slab, band) lines per thread whose second class waits
+// in registers; the plane kernel and the host's overflow sizing both use it.
+constexpr int kPairRegLines = 1;
+
 struct AxisDev {
   int n;
   int nst;
@@ -66,6 +70,9 @@ struct KArgs {
   int plane32;       // every per-plane region (grid plane, column plane, class
                      // partials of a plane) spans less than 2 GiB
   int k1buf;         // every sphere's coefficients and column region span less than 4 GiB
+  int qc;            // inverse band-inner plane tasks: y classes per task (1, or 2: r and r + n1/2)
+  int ovf_lines;     // class pairs: lines per task whose second class waits in the overflow scratch
+  int64_t ovf_off;   // class pairs: element offset of the overflow scratch in the column scratch
   AxisDev ax, ay, az;
   const SphereDesc* sph;
   const int32_t* gidx;

@@ -209,7 +209,9 @@ __device__ void k1r_task(const KArgs& a, int t) {
 // Inverse: the row's occupied x values come from the class slab S[xi][k2][bl]
 // in LDS (zero at the other x), the line is transformed, and the whole row is
 // written to plane z of the grid (times the potential with POT).
-template <typename T, int E, int H, bool POT, int BW>
+// EARLY_POT: the potential's loads are issued before the transform (their
+// latency hides behind it); otherwise after it, with fewer live registers.
+template <typename T, int E, int H, bool POT, int BW, bool EARLY_POT = true>
 __device__ __forceinline__ void bl_inv_x(const KArgs& a, const SphereDesc& d, const cpx<T>* S,
                                          const TwEntry<T>* tab, const int* xo, int z, int r,
                                          int b0) {
@@ -233,9 +235,9 @@ __device__ __forceinline__ void bl_inv_x(const KArgs& a, const SphereDesc& d, co
     const bool valid = k2 < m;
     const int y = r + n1 * (valid ? k2 : 0);
     T vp[E];
-    if constexpr (POT) {
-      const T* __restrict__ vrow =
-          reinterpret_cast<const T*>(a.pot) + static_cast<int64_t>(z * ny + y) * nx;
+    const T* __restrict__ vrow =
+        POT ? reinterpret_cast<const T*>(a.pot) + static_cast<int64_t>(z * ny + y) * nx : nullptr;
+    if constexpr (POT && EARLY_POT) {
 #pragma unroll
       for (int k = 0; k < E; ++k) vp[k] = vrow[k + E * q];
     }
@@ -251,6 +253,10 @@ __device__ __forceinline__ void bl_inv_x(const KArgs& a, const SphereDesc& d, co
     }
     bline_fft<E, H, +1, T>(v, ctx);
     if constexpr (POT) {
+      if constexpr (!EARLY_POT) {
+#pragma unroll
+        for (int k = 0; k < E; ++k) vp[k] = vrow[k + E * q];
+      }
 #pragma unroll
       for (int k = 0; k < E; ++k) v[k] = cscale(v[k], vp[k]);
     }
@@ -333,15 +339,26 @@ __device__ __forceinline__ void bl_stage_xoff(const KArgs& a, const SphereDesc& 
 // slots are laid out in zero-padded blocks of M consecutive y per slab; one
 // thread folds and transforms a whole (slab, band) line in registers.
 // M == 0: generic fold.
-template <typename T, int E, int H, bool MF, int M, bool POT, bool BL, int BWK>
+// QC == 2 (band-inner, M > 0): the task makes classes r and r2 = r + n1/2 from
+// the same column reads, since w_n1^{tb*r2} = (-1)^tb * w_n1^{tb*r}: every
+// loaded block is accumulated twice, with the sign of odd blocks flipped for
+// r2. The transformed lines of r2 wait in registers (NLR lines per thread;
+// the lines past NLR*blockDim in the plan's overflow scratch, one region per
+// task) while the rows of class r are x-transformed, then fill the slab for
+// the rows of r2. Half the tasks read the plane's columns.
+template <typename T, int E, int H, bool MF, int M, bool POT, bool BL, int BWK, int QC>
 __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S, const TwEntry<T>* tab, int* xo) {
   constexpr int L = log2_const<H>();
+  constexpr bool PAIR = QC == 2;
+  static_assert(QC == 1 || (QC == 2 && BL && M > 0), "class pairs: band-inner register fold only");
   const int s = find_sphere_k2r(a, t);
   const SphereDesc d = a.sph[s];
   const int lt = t - d.k2_start;
   const int n1 = a.n1, m = a.m;
-  const int r = lt % n1;
-  const int rest0 = lt / n1;
+  const int ncls = PAIR ? (n1 >> 1) : n1;  // tasks per (plane, chunk)
+  const int r = lt % ncls;
+  const int r2 = r + (n1 >> 1);            // the second class (QC == 2)
+  const int rest0 = lt / ncls;
   // band-inner plane tasks may take a narrower band chunk than the column kernel
   const int nchunk = BL ? d.nchunk2 : d.nchunk;
   const int chunk = rest0 % nchunk, z = rest0 / nchunk;
@@ -368,8 +385,10 @@ __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S, const TwEntry<T>*
     int32_t* tn = tl + ((nslab * n1 + 3) & ~3);  // 16-byte aligned regions
     int32_t* tord = tn + ((nslab + 3) & ~3);     // the slab order
     cpx<T>* troot = reinterpret_cast<cpx<T>*>(tord + ((nslab + 3) & ~3));
-    // the class twiddles w_ny^{k*r}, k < M (FP32: hi and lo of each)
+    // the class twiddles w_ny^{k*r}, k < M (FP32: hi and lo of each), then
+    // those of r2 (QC == 2)
     cpx<T>* ttw = troot + 2 * n1;
+    cpx<T>* ttw2 = ttw + 2 * M;
     {
       const int32_t* __restrict__ blk = a.slab_blk + d.sl_off * n1;
       const int32_t* __restrict__ nblk = a.slab_nblk + d.sl_off;
@@ -393,9 +412,14 @@ __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S, const TwEntry<T>*
       for (int k = threadIdx.x; k < M; k += blockDim.x) {
         if constexpr (std::is_same<T, double>::value) {
           ttw[k] = twf[k * r];
+          if constexpr (PAIR) ttw2[k] = twf[k * r2];
         } else {
           ttw[2 * k] = twf[k * r];
           ttw[2 * k + 1] = twfl[k * r];
+          if constexpr (PAIR) {
+            ttw2[2 * k] = twf[k * r2];
+            ttw2[2 * k + 1] = twfl[k * r2];
+          }
         }
       }
       if constexpr (BL) bl_stage_xoff(a, d, xo);
@@ -406,7 +430,7 @@ __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S, const TwEntry<T>*
     // for blocks of 32)
     constexpr int NBF = FFTB_FOLD_BLOCKS > 0
                             ? FFTB_FOLD_BLOCKS
-                            : ((M > 16 || (BL && std::is_same<T, float>::value)) ? 1 : 2);
+                            : ((M > 16 || PAIR || (BL && std::is_same<T, float>::value)) ? 1 : 2);
     static_assert(NBF >= 1, "fold blocks per round trip");
     // the plane's column scratch as a buffer (the host keeps it below 2 GiB):
     // a block's M loads share one offset register
@@ -416,22 +440,28 @@ __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S, const TwEntry<T>*
     // FB bands per lane: complex64 band-inner folds of blocks up to 16 take two
     // adjacent bands per lane (one 16-byte load each), halving the load
     // instructions
-    constexpr int FB = (BL && std::is_same<T, float>::value && M <= 16) ? 2 : 1;
+    constexpr int FB = (BL && std::is_same<T, float>::value && M <= 16 && !PAIR) ? 2 : 1;
     constexpr int FBL = FB == 2 ? 1 : 0;
     const int nlines = nslab << (bcl - FBL);
-    for (int it = threadIdx.x; it < nlines; it += blockDim.x) {
+    // fold line `it` into u (class r) and, for class pairs, u2 (class r2)
+    auto fold_line = [&](int it, cpx<T> (&u)[FB][M], cpx<T> (&u2)[M]) {
       const int bl = (it & (bmask >> FBL)) << FBL;
       const int xi = tord[it >> (bcl - FBL)];
       const int nh = tn[xi];
       const int32_t* lst = tl + xi * n1;
-      cpx<T> u[FB][M];
 #pragma unroll
       for (int f = 0; f < FB; ++f)
 #pragma unroll
         for (int k = 0; k < M; ++k) u[f][k] = cpx<T>{0, 0};
+      if constexpr (PAIR) {
+#pragma unroll
+        for (int k = 0; k < M; ++k) u2[k] = cpx<T>{0, 0};
+      }
       auto accumulate = [&](const cpx<T> (*v)[M], int tb, bool use) {
         cpx<T> w = troot[2 * tb];
         if (!use) w = cpx<T>{0, 0};
+        // r2's root: the sign of odd blocks flipped
+        const T sg = (tb & 1) ? static_cast<T>(-1) : static_cast<T>(1);
         if constexpr (std::is_same<T, float>::value) {
           cpx<T> wl = troot[2 * tb + 1];
           if (!use) wl = cpx<T>{0, 0};
@@ -439,9 +469,19 @@ __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S, const TwEntry<T>*
           for (int f = 0; f < FB; ++f)
 #pragma unroll
             for (int k = 0; k < M; ++k) u[f][k] = cmac_hl(u[f][k], v[f][k], w, wl);
+          if constexpr (PAIR) {
+            const cpx<T> w2{sg * w.re, sg * w.im}, wl2{sg * wl.re, sg * wl.im};
+#pragma unroll
+            for (int k = 0; k < M; ++k) u2[k] = cmac_hl(u2[k], v[0][k], w2, wl2);
+          }
         } else {
 #pragma unroll
           for (int k = 0; k < M; ++k) u[0][k] = cmac(u[0][k], v[0][k], w);
+          if constexpr (PAIR) {
+            const cpx<T> w2{sg * w.re, sg * w.im};
+#pragma unroll
+            for (int k = 0; k < M; ++k) u2[k] = cmac(u2[k], v[0][k], w2);
+          }
         }
       };
       auto off_of = [&](int e) {
@@ -467,18 +507,24 @@ __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S, const TwEntry<T>*
 #pragma unroll
         for (int b = 0; b < NBF; ++b) accumulate(vb[b], eb[b] & 1023, i + b < nh);
       }
-      cpx<T>* line = S + xi * sx + bl;
+    };
+    // class twiddles w_ny^{k*r} (tw = ttw) or w_ny^{k*r2} (tw = ttw2), then the
+    // length-M IFFT
+    auto finish = [&](cpx<T> (&u)[M], const cpx<T>* tw) {
+      if constexpr (std::is_same<T, double>::value) {
 #pragma unroll
-      for (int f = 0; f < FB; ++f) {
-        if constexpr (std::is_same<T, double>::value) {
+        for (int k = 1; k < M; ++k) u[k] = twmul<+1>(u[k], tw, tw, k);
+      } else {
 #pragma unroll
-          for (int k = 1; k < M; ++k) u[f][k] = twmul<+1>(u[f][k], ttw, ttw, k);
-        } else {
-#pragma unroll
-          for (int k = 1; k < M; ++k) u[f][k] = twmul<+1>(u[f][k], ttw, ttw + 1, 2 * k);
-        }
-        dft<M, +1>(u[f]);
+        for (int k = 1; k < M; ++k) u[k] = twmul<+1>(u[k], tw, tw + 1, 2 * k);
       }
+      dft<M, +1>(u);
+    };
+    // write the M outputs of line `it` (FB adjacent bands) to the class slab
+    auto store_line = [&](int it, const cpx<T> (&u)[FB][M]) {
+      const int bl = (it & (bmask >> FBL)) << FBL;
+      const int xi = tord[it >> (bcl - FBL)];
+      cpx<T>* line = S + xi * sx + bl;
 #pragma unroll
       for (int k = 0; k < M; ++k) {
         if constexpr (FB == 2) {
@@ -488,8 +534,76 @@ __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S, const TwEntry<T>*
           line[k << bcl] = u[0][k];
         }
       }
+    };
+    if constexpr (!PAIR) {
+      for (int it = threadIdx.x; it < nlines; it += blockDim.x) {
+        cpx<T> u[FB][M], u2[M];  // (u2: class pairs only)
+        fold_line(it, u, u2);
+#pragma unroll
+        for (int f = 0; f < FB; ++f) finish(u[f], ttw);
+        store_line(it, u);
+      }
+      __syncthreads();
+    } else {
+      // lines past the register lines first (their r2 outputs go to the
+      // overflow scratch), then the register lines, so that waiting r2 lines
+      // stay live across as few folds as possible
+      constexpr int NLR = kPairRegLines;
+      const int nreg = NLR * static_cast<int>(blockDim.x);
+      const int ovl = a.ovf_lines;
+      cpx<T>* __restrict__ ovf =
+          reinterpret_cast<cpx<T>*>(a.col) + a.ovf_off + static_cast<int64_t>(t) * M * ovl;
+      for (int it = nreg + threadIdx.x; it < nlines; it += blockDim.x) {
+        cpx<T> u[1][M], u2[M];
+        fold_line(it, u, u2);
+        finish(u[0], ttw);
+        store_line(it, u);
+        finish(u2, ttw2);
+        const int j = it - nreg;
+#pragma unroll
+        for (int k = 0; k < M; ++k) ovf[k * ovl + j] = u2[k];
+      }
+      cpx<T> hB[NLR][M];
+#pragma unroll
+      for (int li = 0; li < NLR; ++li) {
+        const int it = threadIdx.x + li * static_cast<int>(blockDim.x);
+        if (it < nlines) {
+          cpx<T> u[1][M];
+          fold_line(it, u, hB[li]);
+          finish(u[0], ttw);
+          store_line(it, u);
+          finish(hB[li], ttw2);
+        }
+      }
+      __syncthreads();
+      // rows of class r, then the waiting lines of r2 into the slab and its
+      // rows (one copy of the x phase: two would keep each other's constants)
+#pragma unroll 1
+      for (int c = 0; c < 2; ++c) {
+        bl_inv_x<T, E, H, POT, BWK, false>(a, d, S, tab, xo, z, c == 0 ? r : r2, b0);
+        if (c == 1) break;
+        __syncthreads();
+#pragma unroll
+        for (int li = 0; li < NLR; ++li) {
+          const int it = threadIdx.x + li * static_cast<int>(blockDim.x);
+          if (it < nlines) {
+            cpx<T> u[1][M];
+#pragma unroll
+            for (int k = 0; k < M; ++k) u[0][k] = hB[li][k];
+            store_line(it, u);
+          }
+        }
+        for (int it = nreg + threadIdx.x; it < nlines; it += blockDim.x) {
+          const int j = it - nreg;
+          cpx<T> u[1][M];
+#pragma unroll
+          for (int k = 0; k < M; ++k) u[0][k] = ovf[k * ovl + j];
+          store_line(it, u);
+        }
+        __syncthreads();
+      }
+      return;
     }
-    __syncthreads();
   } else {
     const int32_t* __restrict__ cidx = a.colidx + d.colidx_off;
 
@@ -1012,8 +1126,9 @@ __global__ void __launch_bounds__(256) k1r_kernel(const KArgs a) {
 // the plain transform carries no potential registers)
 // BWK: bands per row of lanes of the band-inner x lines (one 128-byte piece,
 // or half of one for the narrow inverse tiling)
+// QC: y classes per inverse task (2: class pairs sharing the fold's reads)
 template <int S, typename T, int E, int H, bool MF, bool FC, int M, bool BL,
-          int BWK = band_width<T>()>
+          int BWK = band_width<T>(), int QC = 1>
 __global__ void __launch_bounds__(512) k2r_kernel(const KArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
@@ -1034,7 +1149,7 @@ __global__ void __launch_bounds__(512) k2r_kernel(const KArgs a) {
   if (!a.persistent) {
     const int t = static_task_g(a.k2_tasks, a.g2);
     if (t >= 0) {
-      if constexpr (S > 0) k2r_inv_task<T, E, H, MF, M, FC, BL, BWK>(a, t, lds, tab, xo);
+      if constexpr (S > 0) k2r_inv_task<T, E, H, MF, M, FC, BL, BWK, QC>(a, t, lds, tab, xo);
       else if constexpr (FC) k2r_fwd_cls_task<T, E, H, MF, BL, BWK>(a, t, lds, tab, xo);
       else k2r_fwd_task<T, E, H, MF>(a, t, lds);
     }
@@ -1047,7 +1162,7 @@ __global__ void __launch_bounds__(512) k2r_kernel(const KArgs a) {
     const int t = __builtin_amdgcn_readfirstlane(sh_task);
     __syncthreads();
     if (t < 0) break;
-    if constexpr (S > 0) k2r_inv_task<T, E, H, MF, M, FC, BL, BWK>(a, t, lds, tab, xo);
+    if constexpr (S > 0) k2r_inv_task<T, E, H, MF, M, FC, BL, BWK, QC>(a, t, lds, tab, xo);
     else if constexpr (FC) k2r_fwd_cls_task<T, E, H, MF, BL, BWK>(a, t, lds, tab, xo);
     else k2r_fwd_task<T, E, H, MF>(a, t, lds);
     __syncthreads();
@@ -1061,17 +1176,19 @@ __global__ void __launch_bounds__(512) k2r_kernel(const KArgs a) {
 constexpr bool fold_m_compiled(int H, int m) { return (H == 8 || H == 16) && (m == 8 || m == 16); }
 
 template <int S, typename T, int E, int H, bool MF, bool FC, int M, bool BL = false,
-          int BWK = band_width<T>()>
+          int BWK = band_width<T>(), int QC = 1>
 hipError_t launch_k2(const KArgs& a, int grid, int threads, size_t lds, hipStream_t st) {
-  hipLaunchKernelGGL((k2r_kernel<S, T, E, H, MF, FC, M, BL, BWK>), dim3(grid), dim3(threads), lds, st, a);
+  hipLaunchKernelGGL((k2r_kernel<S, T, E, H, MF, FC, M, BL, BWK, QC>), dim3(grid), dim3(threads), lds,
+                     st, a);
   return hipGetLastError();
 }
 
 template <int S, typename T, int E, int H, bool MF, bool FC, int M, bool BL = false,
-          int BWK = band_width<T>()>
+          int BWK = band_width<T>(), int QC = 1>
 hipError_t attr_k2(size_t lds) {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(k2r_kernel<S, T, E, H, MF, FC, M, BL, BWK>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  return hipFuncSetAttribute(
+      reinterpret_cast<const void*>(k2r_kernel<S, T, E, H, MF, FC, M, BL, BWK, QC>),
+      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
 template <int S, typename T, int E, int H, bool MF>

@@ -198,6 +198,22 @@ def test_half_piece_inverse_tiling():
                                      tuning=dict(inv_band_chunk=8, path=3)))
 
 
+def test_inverse_class_pairs_tiling():
+    # the inverse folds two y classes per task (r and r + n1/2) where n1 is
+    # even and the classes have 16 rows; one class per task on request
+    w = synth.make_workload("c2", nbands=1)
+    for dt in ("c128", "c64"):
+        p = host_plan(w.dims, [w.spheres[0].lin], nb=256, dtype=dt, tuning=dict(inv_acc=2))
+        inv = p.info["tuning"]["inv"]
+        assert (inv["y_classes"], inv["acc"], inv["path"]) == (8, 2, 3), inv
+        p = host_plan(w.dims, [w.spheres[0].lin], nb=256, dtype=dt, tuning=dict(inv_acc=1))
+        assert p.info["tuning"]["inv"]["acc"] == 1
+    # classes of 8 cannot pair
+    _expect_status(pk.FFTB_ERR_UNSUPPORTED,
+                   lambda: host_plan(w.dims, [w.spheres[0].lin], nb=256, dtype="c128",
+                                     tuning=dict(inv_acc=2, inv_y_classes=16)))
+
+
 def test_mfma_flag_validation():
     m, lin = synth.sphere_map((128, 16, 128), (20, 4, 20))
     p = pk.Plan((128, 16, 128), [lin], 16, dtype="c64", flags=pk.PLAN_HOST_ONLY | pk.PLAN_MFMA)

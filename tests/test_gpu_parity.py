@@ -107,6 +107,51 @@ def test_band_inner_half_pieces(case, flags):
     p.close()
 
 
+PAIR_VARIANTS = [
+    # (tuning, flags): class pairs (the default where they apply), pairs at 256
+    # threads (lines past the register lines take the overflow scratch),
+    # pairs persistent + graph replayed, one class per task
+    (dict(path=3, inv_acc=2), 0),
+    (dict(path=3, inv_acc=2, inv_threads=256), 0),
+    (dict(path=3, inv_acc=2), 5),
+    (dict(path=3, inv_acc=1), 0),
+]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("vi", range(len(PAIR_VARIANTS)))
+@pytest.mark.parametrize("case", range(len(REG_CASES)))
+def test_band_inner_class_pairs(case, vi, dtype):
+    """Inverse plane tasks folding two y classes r and r + n1/2 from the same
+    column reads (the second class's lines waiting in registers or in the
+    overflow scratch), against the oracle; then the fused potential step."""
+    import oracle
+    import torch
+    from gpu_util import make_plan, to_device, split_sphere
+    dims, semi, kpts, nb, seed = REG_CASES[case]
+    tun, flags = PAIR_VARIANTS[vi]
+    w = synth.small_workload(dims, semi, kpts, nb + 9, seed=seed + 40, shuffle=True)
+    p = make_plan(w, dtype=dtype, flags=flags, tuning=tun)
+    inv = p.info["tuning"]["inv"]
+    assert inv["path"] == 3 and inv["acc"] == tun["inv_acc"], inv
+    p.close()
+    e = check_workload(w, dtype, flags=flags, tuning=tun, reps=2)
+    print(dims, dtype, tun, flags, e)
+    assert max(e) <= TOL[dtype], e
+    npdt = np.complex128 if dtype == "c128" else np.complex64
+    rdt = np.float64 if dtype == "c128" else np.float32
+    v = np.random.default_rng(79).standard_normal(dims[::-1]).astype(rdt)
+    coeffs = [c.astype(npdt) for c in w.coeffs]
+    p = make_plan(w, dtype=dtype, flags=flags, tuning=tun)
+    sph = to_device(np.concatenate([c.reshape(-1) for c in coeffs]), dtype)
+    out = p.apply_potential(sph, torch.from_numpy(v.reshape(-1)).to("cuda"))
+    torch.cuda.synchronize()
+    for s, c, o in zip(w.spheres, coeffs, split_sphere(w, out.cpu().numpy())):
+        ref = oracle.apply_potential(dims, s.lin, c.astype(np.complex128), v.astype(np.float64))
+        assert rel(o, ref) <= TOL[dtype], (rel(o, ref), dtype, tun)
+    p.close()
+
+
 TUNINGS = [
     dict(band_chunk=1), dict(band_chunk=2, threads=64), dict(band_chunk=4, col_tile=3),
     dict(band_chunk=16, threads=128), dict(y_classes=2, x_rows=1), dict(y_classes=5, x_rows=2),
