@@ -842,7 +842,9 @@ void build_descs(fftb_plan_s& P, DirCfg& D) {
   D.ovf_off = 0;
   if (D.qc == 2) {
     for (auto& s : P.sph)
-      D.ovf_lines = std::max(D.ovf_lines, s.nslab * bc2 - kPairRegLines * D.threads);
+      D.ovf_lines = std::max(D.ovf_lines, s.nslab * bc2 - (P.dtype == FFTB_C64 ? kPairRegLines<float>
+                                                                              : kPairRegLines<double>) *
+                                                                 D.threads);
     D.ovf_off = D.col_elems;
     D.col_elems += static_cast<int64_t>(k2) * D.m * D.ovf_lines;
   }

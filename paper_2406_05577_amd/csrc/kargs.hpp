@@ -9,7 +9,8 @@ constexpr int kAxisStages = 8;
 
 // Inverse class pairs: (slab, band) lines per thread whose second class waits
 // in registers; the plane kernel and the host's overflow sizing both use it.
-constexpr int kPairRegLines = 1;
+template <typename T>
+constexpr int kPairRegLines = sizeof(T) == 4 ? 2 : 1;
 
 struct AxisDev {
   int n;

@@ -548,7 +548,7 @@ __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S, const TwEntry<T>*
       // lines past the register lines first (their r2 outputs go to the
       // overflow scratch), then the register lines, so that waiting r2 lines
       // stay live across as few folds as possible
-      constexpr int NLR = kPairRegLines;
+      constexpr int NLR = kPairRegLines<T>;
       const int nreg = NLR * static_cast<int>(blockDim.x);
       const int ovl = a.ovf_lines;
       cpx<T>* __restrict__ ovf =
