@@ -1342,8 +1342,8 @@ DirKey dir_key(const DirCfg& D, bool inverse) {
 // Candidate tilings of one direction around the library defaults, most
 // promising first: band chunk (default, half, and twice for the inverse),
 // class count (default, ny/16, ny/8), 256 or 512 threads, the 8-lane line
-// shapes, and for the forward the class-partial and the LDS-accumulator
-// variants. The LDS-stage kernels are tried only where an axis has no
+// shapes, for the inverse class pairs or one class per task, and for the
+// forward the class-partial and the LDS-accumulator variants. The LDS-stage kernels are tried only where an axis has no
 // register shape. Candidates that resolve to the same tiling, or that do not
 // fit, are dropped; at most `cap` remain.
 std::vector<fftb_dir_tuning> candidates(fftb_plan_s& P, bool inverse, const fftb_dir_tuning& base,
@@ -1372,7 +1372,12 @@ std::vector<fftb_dir_tuning> candidates(fftb_plan_s& P, bool inverse, const fftb
           t.path = 0;
           t.lanes = lanes;
           if (inverse) {
-            raw.push_back(t);
+            // band-inner: class pairs (the default where they apply) and one
+            // class per task
+            for (int acc : {0, 1}) {
+              t.acc = acc;
+              raw.push_back(t);
+            }
           } else {
             for (int acc : {3, 1}) {
               t.acc = acc;
