@@ -60,6 +60,17 @@ __device__ void bl_fill_twiddles(TwEntry<T>* tab, const cpx<T>* __restrict__ roo
   }
 }
 
+// Ordering point between groups of a line's values: the values k0 .. k1-1 are
+// complete here, and everything that reads them, or reads memory, comes after.
+// (Scheduling barriers alone did not keep the groups apart: the compiler
+// issued all table reads and all partner fetches of a line at once, holding a
+// second copy of the line in registers.)
+template <typename T>
+__device__ __forceinline__ void bl_fence(cpx<T>* v, int k0, int k1) {
+#pragma unroll
+  for (int k = k0; k < k1; ++k) asm volatile("" : "+v"(v[k].re), "+v"(v[k].im)::"memory");
+}
+
 template <int E, int H, int S, typename T, int BW = band_width<T>()>
 struct BLineCtx {
   static constexpr int kBW = BW;  // bands per row of lanes
@@ -113,7 +124,7 @@ __device__ __forceinline__ void bl_rounds(cpx<T>* v, const BLineCtx<E, H, S, T, 
       for (int k = 0; k < E; ++k) {
         const T pr = lane_read(src, v[k].re), pi = lane_read(src, v[k].im);
         v[k] = {ffma(sg, v[k].re, pr), ffma(sg, v[k].im, pi)};
-        if ((k & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+        if ((k & 3) == 3 && k + 1 < E) bl_fence(v, k - 3, k + 5 < E ? k + 5 : E);
       }
     }
     if constexpr (HS == 2) {
@@ -150,7 +161,7 @@ __device__ __forceinline__ void bline_fft(cpx<T>* v, const BLineCtx<E, H, S, T, 
         v[k] = cmul_hl(v[k], cpx<float>{w.re, w.im}, cpx<float>{w.lre, w.lim});
       else
         v[k] = cmul(v[k], cpx<double>{w.re, w.im});
-      if ((k & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+      if ((k & 3) == 3 && k + 1 < E) bl_fence(v, k - 3, k + 1);
     }
     bl_rounds<H / 2, 0, E, H, S, T, BW>(v, c);
   }

@@ -319,6 +319,9 @@ __device__ __forceinline__ void dft_pfa(cpx<T>* v) {
 #pragma unroll
     for (int k2 = 0; k2 < B; ++k2) u[n1 * B + k2] = t[k2];
   });
+  // long codelets: keep the scheduler from interleaving the two stages (it
+  // would hold both arrays live: 2R values)
+  if constexpr (R >= 36) __builtin_amdgcn_sched_barrier(0);
   constexpr int cb = B * inv_mod(B % A, A), ca = A * inv_mod(A % B, B);
   static_for<0, B>([&](auto j2) {
     constexpr int k2 = decltype(j2)::value;
