@@ -476,7 +476,9 @@ fftb_status choose_dir(fftb_plan_s& P, int d, const fftb_dir_tuning& t) {
         D.zline = P.max_nslab * sx;
         D.class_par = true;
         D.fwd_cls = !inverse;
-        D.fold_m = inverse ? D.m : 0;
+        // inverse: the fold's class length; forward: the y transform's, where
+        // compiled (8, 12, 16)
+        D.fold_m = (inverse || D.m == 8 || D.m == 12 || D.m == 16) ? D.m : 0;
         D.acc_lds = false;
         D.nsplit = 1;
         std::vector<int> rad;

@@ -171,7 +171,18 @@ hipError_t bil_plane(const KArgs& a, int grid, int threads, size_t lds, hipStrea
                  : launch_k2<S, T, E, H, false, false, 16, true>(a, grid, threads, lds, st);
     return hipErrorInvalidValue;
   } else {
-    if (attr_only) return attr_k2<S, T, E, H, false, true, 0, true>(lds);
+    // forward: class partials, the y transform of length 8, 12 or 16 compiled
+    // (0: any codelet length)
+    if (attr_only) {
+      hipError_t e = attr_k2<S, T, E, H, false, true, 0, true>(lds);
+      if (e == hipSuccess) e = attr_k2<S, T, E, H, false, true, 8, true>(lds);
+      if (e == hipSuccess) e = attr_k2<S, T, E, H, false, true, 12, true>(lds);
+      if (e == hipSuccess) e = attr_k2<S, T, E, H, false, true, 16, true>(lds);
+      return e;
+    }
+    if (fold_m == 8) return launch_k2<S, T, E, H, false, true, 8, true>(a, grid, threads, lds, st);
+    if (fold_m == 12) return launch_k2<S, T, E, H, false, true, 12, true>(a, grid, threads, lds, st);
+    if (fold_m == 16) return launch_k2<S, T, E, H, false, true, 16, true>(a, grid, threads, lds, st);
     return launch_k2<S, T, E, H, false, true, 0, true>(a, grid, threads, lds, st);
   }
 }

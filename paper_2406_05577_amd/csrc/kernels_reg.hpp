@@ -794,7 +794,8 @@ __device__ __forceinline__ void fwd_x_rows(const KArgs& a, const cpx<T>* __restr
 // Class-parallel forward task (plane z, chunk, class r): x transform of the
 // class rows, y transform of length m per (slab, band) line, then the class
 // partial Z_r[xi][j] = w_ny^{-j*r} * Y[xi][j] stored as Z[z][xi][j][r][band].
-template <typename T, int E, int H, bool MF, bool BL, int BWK>
+// M > 0 (band-inner): the class length is a compile-time constant.
+template <typename T, int E, int H, bool MF, bool BL, int BWK, int M>
 __device__ void k2r_fwd_cls_task(const KArgs& a, int t, cpx<T>* S, const TwEntry<T>* tab, int* xo) {
   const int s = find_sphere_k2r(a, t);
   const SphereDesc d = a.sph[s];
@@ -838,18 +839,22 @@ __device__ void k2r_fwd_cls_task(const KArgs& a, int t, cpx<T>* S, const TwEntry
     const unsigned jstride = __builtin_amdgcn_readfirstlane(
         static_cast<unsigned>(n1 * nbp) * static_cast<unsigned>(sizeof(cpx<T>)));
     const int nlines = nslab << bcl;
+    constexpr int MU = M > 0 ? M : kMaxRadixDev;
     for (int it = threadIdx.x; it < nlines; it += blockDim.x) {
       const int bl = it & bmask, xi = it >> bcl;
       const cpx<T>* line = S + xi * sx + bl;
-      cpx<T> u[kMaxRadixDev];
+      cpx<T> u[MU];
 #pragma unroll
-      for (int j = 0; j < kMaxRadixDev; ++j)
-        if (j < m) u[j] = line[j << bcl];
-      butterfly<-1>(m, u);
+      for (int j = 0; j < MU; ++j)
+        if (M > 0 || j < m) u[j] = line[j << bcl];
+      if constexpr (M > 0)
+        dft<M, -1>(u);
+      else
+        butterfly<-1>(m, u);
       unsigned o = static_cast<unsigned>(xi * ny * nbp + bl) * static_cast<unsigned>(sizeof(cpx<T>));
 #pragma unroll
-      for (int j = 0; j < kMaxRadixDev; ++j) {
-        if (j < m) {
+      for (int j = 0; j < MU; ++j) {
+        if (M > 0 || j < m) {
           const cpx<T> val = std::is_same<T, double>::value ? twmul<-1>(u[j], ttw, ttw, j)
                                                            : twmul<-1>(u[j], ttw, ttw + 1, 2 * j);
           buf_store_nt(rz, val, o);
@@ -1150,7 +1155,7 @@ __global__ void __launch_bounds__(512) k2r_kernel(const KArgs a) {
     const int t = static_task_g(a.k2_tasks, a.g2);
     if (t >= 0) {
       if constexpr (S > 0) k2r_inv_task<T, E, H, MF, M, FC, BL, BWK, QC>(a, t, lds, tab, xo);
-      else if constexpr (FC) k2r_fwd_cls_task<T, E, H, MF, BL, BWK>(a, t, lds, tab, xo);
+      else if constexpr (FC) k2r_fwd_cls_task<T, E, H, MF, BL, BWK, M>(a, t, lds, tab, xo);
       else k2r_fwd_task<T, E, H, MF>(a, t, lds);
     }
     return;
@@ -1163,7 +1168,7 @@ __global__ void __launch_bounds__(512) k2r_kernel(const KArgs a) {
     __syncthreads();
     if (t < 0) break;
     if constexpr (S > 0) k2r_inv_task<T, E, H, MF, M, FC, BL, BWK, QC>(a, t, lds, tab, xo);
-    else if constexpr (FC) k2r_fwd_cls_task<T, E, H, MF, BL, BWK>(a, t, lds, tab, xo);
+    else if constexpr (FC) k2r_fwd_cls_task<T, E, H, MF, BL, BWK, M>(a, t, lds, tab, xo);
     else k2r_fwd_task<T, E, H, MF>(a, t, lds);
     __syncthreads();
   }
