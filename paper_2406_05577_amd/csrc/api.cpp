@@ -396,15 +396,17 @@ fftb_status choose_dir(fftb_plan_s& P, int d, const fftb_dir_tuning& t) {
   D.qc = 1;
   D.threads = threads;
   D.bil1 = D.bil2 = false;
+  D.mf1 = D.mf2 = false;
   // ---- band-inner lines (path 3, and the default where the shapes exist):
   // the band chunk is one 128-byte piece; the complex64 inverse plane kernel
   // may take half of one (band_chunk = 8: x lines over twice the positions,
   // the fold over classes of 16 or 32; the column kernel keeps whole pieces)
   const int bw = fp64 ? 8 : 16;
   const bool narrow = inverse && t.band_chunk == bw / 2;
+  const bool mfma = (P.flags & FFTB_PLAN_MFMA) != 0;
   const bool bil_ok = (t.path == 0 || t.path == 3) &&
                       (t.band_chunk == 0 || t.band_chunk == bw || narrow) && (t.lanes == 0) &&
-                      !(P.flags & FFTB_PLAN_MFMA) && bil_regions_fit(P, bw);
+                      !(mfma && fp64) && bil_regions_fit(P, bw);
   if (bil_ok) {
     int e1 = 0, h1 = 0, e2 = 0, h2 = 0;
     // the column kernel takes the band-inner shape of z, else a register shape
@@ -441,6 +443,15 @@ fftb_status choose_dir(fftb_plan_s& P, int d, const fftb_dir_tuning& t) {
         }
         if (best_n1) break;
       }
+      // with FFTB_PLAN_MFMA the inverse takes band-inner lines only with its
+      // fold of length 16 on the matrix cores, the forward only where the
+      // register lines have no matrix-core stage
+      const bool mf_fold = mfma && inverse && !narrow && best_n1 && P.ny / best_n1 == 16;
+      if (mfma && inverse && !mf_fold) best_n1 = 0;
+      if (mfma && !inverse) {
+        int er = 0, hr = 0;
+        if (reg_shape(P.nx, fp64, er, hr, 8, false) && mfma_shape_supported(fp64, er, hr)) best_n1 = 0;
+      }
       if (best_n1) {
         // inverse class pairs (r, r + n1/2 per task: one read of the plane's
         // columns serves both) where the fold has length 16 and the second
@@ -454,6 +465,8 @@ fftb_status choose_dir(fftb_plan_s& P, int d, const fftb_dir_tuning& t) {
           return fail(FFTB_ERR_UNSUPPORTED, "class pairs need an even class count with classes of 16");
         best_b = plane_lds_bil(P, best_n1, bwp, e2, h2, inverse, sx, tab_at, tw_at, pair);
         D.qc = pair ? 2 : 1;
+        D.mf1 = false;
+        D.mf2 = mf_fold;
         D.bc = bw;
         D.bc2 = bwp;
         D.narrow = narrow;
@@ -492,7 +505,9 @@ fftb_status choose_dir(fftb_plan_s& P, int d, const fftb_dir_tuning& t) {
         return FFTB_OK;
       }
     }
-    if (t.path == 3) return fail(FFTB_ERR_UNSUPPORTED, "no band-inner line shape or class split fits");
+    if (t.path == 3)
+      return fail(FFTB_ERR_UNSUPPORTED, mfma ? "no band-inner plan with a matrix-core stage fits"
+                                             : "no band-inner line shape or class split fits");
   }
   // ---- column kernel
   int e1 = 0, h1 = 0;
@@ -1029,6 +1044,7 @@ KArgs make_args(const fftb_plan_s& P, const DirCfg& D, const void* in, void* out
   a.fwd_cls = D.fwd_cls ? 1 : 0;
   a.g2 = D.reg2 ? (D.class_par ? D.n1 / D.qc : D.nsplit) : 1;
   a.qc = D.qc;
+  a.mfma = (D.bil2 && D.mf2) ? 1 : 0;
   a.ovf_lines = D.ovf_lines;
   a.ovf_off = D.ovf_off;
   // 32-bit buffer addressing where every region it covers allows it
@@ -1589,6 +1605,8 @@ fftb_status fftb_plan_create(fftb_plan* out, const int32_t dims[3], const fftb_s
       fftb_status st = choose_dir(*P, d, d == 0 ? t.inv : t.fwd);
       if (st != FFTB_OK) return st;
     }
+    if ((flags & FFTB_PLAN_MFMA) && !(P->dir[0].mf1 || P->dir[0].mf2 || P->dir[1].mf1 || P->dir[1].mf2))
+      return fail(FFTB_ERR_UNSUPPORTED, "no DFT_16 stage for the matrix cores in this plan");
     P->pad_m = P->dir[0].fold_m;
     build_slots(*P);
     for (int d = 0; d < 2; ++d) build_descs(*P, P->dir[d]);

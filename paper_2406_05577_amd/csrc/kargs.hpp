@@ -72,6 +72,7 @@ struct KArgs {
                      // partials of a plane) spans less than 2 GiB
   int k1buf;         // every sphere's coefficients and column region span less than 4 GiB
   int qc;            // inverse band-inner plane tasks: y classes per task (1, or 2: r and r + n1/2)
+  int mfma;          // band-inner plane kernel: length-16 fold transforms on the matrix cores
   int ovf_lines;     // class pairs: lines per task whose second class waits in the overflow scratch
   int64_t ovf_off;   // class pairs: element offset of the overflow scratch in the column scratch
   AxisDev ax, ay, az;

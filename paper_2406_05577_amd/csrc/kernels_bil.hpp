@@ -142,12 +142,14 @@ hipError_t bil_launch_k1(const KArgs& a, int grid, int threads, hipStream_t st) 
 
 // Plane kernel on band-inner x lines: inverse with the register fold of class
 // length 8 or 16 (with or without the potential), forward with class partials.
-// Class pairs (a.qc == 2) with the fold of length 16.
+// Class pairs (a.qc == 2) with the fold of length 16; complex64 folds of
+// length 16 on the matrix cores (a.mfma).
 template <int S, typename T, int E, int H>
 hipError_t bil_plane(const KArgs& a, int grid, int threads, size_t lds, hipStream_t st, int fold_m,
                      bool attr_only) {
   if constexpr (S > 0) {
     constexpr int BW = band_width<T>();
+    constexpr bool f32 = std::is_same<T, float>::value;
     if (attr_only) {
       hipError_t e = attr_k2<S, T, E, H, false, false, 8, true>(lds);
       if (e == hipSuccess) e = attr_k2<S, T, E, H, false, false, 16, true>(lds);
@@ -155,9 +157,25 @@ hipError_t bil_plane(const KArgs& a, int grid, int threads, size_t lds, hipStrea
       if (e == hipSuccess) e = attr_k2<S, T, E, H, false, true, 16, true>(lds);
       if (e == hipSuccess) e = attr_k2<S, T, E, H, false, false, 16, true, BW, 2>(lds);
       if (e == hipSuccess) e = attr_k2<S, T, E, H, false, true, 16, true, BW, 2>(lds);
+      if constexpr (f32) {
+        if (e == hipSuccess) e = attr_k2<S, T, E, H, true, false, 16, true>(lds);
+        if (e == hipSuccess) e = attr_k2<S, T, E, H, true, true, 16, true>(lds);
+        if (e == hipSuccess) e = attr_k2<S, T, E, H, true, false, 16, true, BW, 2>(lds);
+        if (e == hipSuccess) e = attr_k2<S, T, E, H, true, true, 16, true, BW, 2>(lds);
+      }
       return e;
     }
     const bool pot = a.pot != nullptr;
+    if constexpr (f32) {
+      if (a.mfma) {
+        if (fold_m != 16) return hipErrorInvalidValue;
+        if (a.qc == 2)
+          return pot ? launch_k2<S, T, E, H, true, true, 16, true, BW, 2>(a, grid, threads, lds, st)
+                     : launch_k2<S, T, E, H, true, false, 16, true, BW, 2>(a, grid, threads, lds, st);
+        return pot ? launch_k2<S, T, E, H, true, true, 16, true>(a, grid, threads, lds, st)
+                   : launch_k2<S, T, E, H, true, false, 16, true>(a, grid, threads, lds, st);
+      }
+    }
     if (a.qc == 2) {
       if (fold_m != 16) return hipErrorInvalidValue;
       return pot ? launch_k2<S, T, E, H, false, true, 16, true, BW, 2>(a, grid, threads, lds, st)

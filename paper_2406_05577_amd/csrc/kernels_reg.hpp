@@ -444,11 +444,17 @@ __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S, const TwEntry<T>*
     constexpr int FB = (BL && std::is_same<T, float>::value && M <= 16 && !PAIR) ? 2 : 1;
     constexpr int FBL = FB == 2 ? 1 : 0;
     const int nlines = nslab << (bcl - FBL);
+    // MF (band-inner, complex64, M == 16): the length-16 IFFT of the lines on
+    // the matrix cores, which every lane of a wave takes part in: the line
+    // loops run to whole waves, and lanes past the last line fold nothing
+    constexpr bool MFB = MF && BL && M == 16 && std::is_same<T, float>::value;
+    const int nlines_w = MFB ? ((nlines + 63) & ~63) : nlines;
     // fold line `it` into u (class r) and, for class pairs, u2 (class r2)
     auto fold_line = [&](int it, cpx<T> (&u)[FB][M], cpx<T> (&u2)[M]) {
+      const bool live = it < nlines;
       const int bl = (it & (bmask >> FBL)) << FBL;
-      const int xi = tord[it >> (bcl - FBL)];
-      const int nh = tn[xi];
+      const int xi = live ? tord[it >> (bcl - FBL)] : 0;
+      const int nh = live ? tn[xi] : 0;
       const int32_t* lst = tl + xi * n1;
 #pragma unroll
       for (int f = 0; f < FB; ++f)
@@ -519,7 +525,10 @@ __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S, const TwEntry<T>*
 #pragma unroll
         for (int k = 1; k < M; ++k) u[k] = twmul<+1>(u[k], tw, tw + 1, 2 * k);
       }
-      dft<M, +1>(u);
+      if constexpr (MFB)
+        dft16_mfma<+1>(u);
+      else
+        dft<M, +1>(u);
     };
     // write the M outputs of line `it` (FB adjacent bands) to the class slab
     auto store_line = [&](int it, const cpx<T> (&u)[FB][M]) {
@@ -537,12 +546,12 @@ __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S, const TwEntry<T>*
       }
     };
     if constexpr (!PAIR) {
-      for (int it = threadIdx.x; it < nlines; it += blockDim.x) {
+      for (int it = threadIdx.x; it < nlines_w; it += blockDim.x) {
         cpx<T> u[FB][M], u2[M];  // (u2: class pairs only)
         fold_line(it, u, u2);
 #pragma unroll
         for (int f = 0; f < FB; ++f) finish(u[f], ttw);
-        store_line(it, u);
+        if (it < nlines) store_line(it, u);
       }
       __syncthreads();
     } else {
@@ -554,26 +563,28 @@ __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S, const TwEntry<T>*
       const int ovl = a.ovf_lines;
       cpx<T>* __restrict__ ovf =
           reinterpret_cast<cpx<T>*>(a.col) + a.ovf_off + static_cast<int64_t>(t) * M * ovl;
-      for (int it = nreg + threadIdx.x; it < nlines; it += blockDim.x) {
+      for (int it = nreg + threadIdx.x; it < nlines_w; it += blockDim.x) {
         cpx<T> u[1][M], u2[M];
         fold_line(it, u, u2);
         finish(u[0], ttw);
-        store_line(it, u);
         finish(u2, ttw2);
-        const int j = it - nreg;
+        if (it < nlines) {
+          store_line(it, u);
+          const int j = it - nreg;
 #pragma unroll
-        for (int k = 0; k < M; ++k) ovf[k * ovl + j] = u2[k];
+          for (int k = 0; k < M; ++k) ovf[k * ovl + j] = u2[k];
+        }
       }
       cpx<T> hB[NLR][M];
 #pragma unroll
       for (int li = 0; li < NLR; ++li) {
         const int it = threadIdx.x + li * static_cast<int>(blockDim.x);
-        if (it < nlines) {
+        if (it < nlines_w) {
           cpx<T> u[1][M];
           fold_line(it, u, hB[li]);
           finish(u[0], ttw);
-          store_line(it, u);
           finish(hB[li], ttw2);
+          if (it < nlines) store_line(it, u);
         }
       }
       __syncthreads();

@@ -222,9 +222,15 @@ def test_mfma_flag_validation():
     _expect_status(pk.FFTB_ERR_UNSUPPORTED,
                    lambda: pk.Plan((128, 16, 128), [lin], 16, dtype="c128",
                                    flags=pk.PLAN_HOST_ONLY | pk.PLAN_MFMA))
+    # classes of 16 give the inverse fold's length-16 transforms to the matrix
+    # cores on any x and z (band-inner lines)
     m2, lin2 = synth.sphere_map((96, 16, 96), (20, 4, 20))
+    p = pk.Plan((96, 16, 96), [lin2], 16, dtype="c64", flags=pk.PLAN_HOST_ONLY | pk.PLAN_MFMA)
+    assert p.info["tuning"]["inv"]["path"] == 3
+    # neither classes of 16 nor 128-point lines: no stage for the matrix cores
+    m3, lin3 = synth.sphere_map((96, 24, 96), (20, 5, 20))
     _expect_status(pk.FFTB_ERR_UNSUPPORTED,
-                   lambda: pk.Plan((96, 16, 96), [lin2], 16, dtype="c64",
+                   lambda: pk.Plan((96, 24, 96), [lin3], 16, dtype="c64",
                                    flags=pk.PLAN_HOST_ONLY | pk.PLAN_MFMA))
 
 

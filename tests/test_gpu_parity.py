@@ -402,9 +402,48 @@ def test_autotune_budget(tmp_path, monkeypatch, capfd):
 @pytest.mark.parametrize("flags", [16, 16 | 1 | 4])
 def test_mfma_radix16(flags):
     """complex64 with the in-lane DFT_16 stages on the matrix cores (FP32
-    v_mfma_f32_32x32x2f32), against the FP64 oracle."""
+    v_mfma_f32_32x32x2f32), against the FP64 oracle: 128-point register lines
+    and the inverse fold of classes of 16 (128^3)."""
     dims, semi, kpts, nb, seed = REG_CASES[2]
     w = synth.small_workload(dims, semi, kpts, 5, seed=seed, shuffle=True)
     e = check_workload(w, "c64", flags=flags, reps=2)
     print("mfma", flags, e)
     assert max(e) <= TOL["c64"], e
+
+
+MFMA_FOLD_CASES = [
+    # the inverse fold's length-16 transforms on the matrix cores on the y axes
+    # of 96 and 160 (classes of 16), one class and class pairs per task,
+    # ragged bands, with the potential; 32^3 has a single class
+    (REG_CASES[1], dict(inv_acc=2)),
+    (REG_CASES[1], dict(inv_acc=1)),
+    (REG_CASES[3], dict()),
+    (REG_CASES[3], dict(inv_acc=2, inv_threads=256)),
+    (REG_CASES[0], dict()),
+]
+
+
+@pytest.mark.parametrize("flags", [16, 16 | 1 | 4])
+@pytest.mark.parametrize("ci", range(len(MFMA_FOLD_CASES)))
+def test_mfma_fold(ci, flags):
+    import oracle
+    import torch
+    from gpu_util import make_plan, to_device, split_sphere
+    (dims, semi, kpts, nb, seed), tun = MFMA_FOLD_CASES[ci]
+    w = synth.small_workload(dims, semi, kpts, nb + 11, seed=seed + 70, shuffle=True)
+    p = make_plan(w, dtype="c64", flags=flags, tuning=tun or None)
+    assert p.info["flags"] & 16 and p.info["tuning"]["inv"]["path"] == 3, p.info["tuning"]
+    p.close()
+    e = check_workload(w, "c64", flags=flags, tuning=tun or None, reps=2)
+    print("mfma fold", dims, tun, flags, e)
+    assert max(e) <= TOL["c64"], e
+    v = np.random.default_rng(80).standard_normal(dims[::-1]).astype(np.float32)
+    coeffs = [c.astype(np.complex64) for c in w.coeffs]
+    p = make_plan(w, dtype="c64", flags=flags, tuning=tun or None)
+    sph = to_device(np.concatenate([c.reshape(-1) for c in coeffs]), "c64")
+    out = p.apply_potential(sph, torch.from_numpy(v.reshape(-1)).to("cuda"))
+    torch.cuda.synchronize()
+    for s, c, o in zip(w.spheres, coeffs, split_sphere(w, out.cpu().numpy())):
+        ref = oracle.apply_potential(dims, s.lin, c.astype(np.complex128), v.astype(np.float64))
+        assert rel(o, ref) <= TOL["c64"], (rel(o, ref), tun, flags)
+    p.close()
