@@ -82,7 +82,10 @@ enum {
                                 far, and print one progress line per trial on stderr */
   FFTB_PLAN_GRAPH = 4,       /* replay each direction as a captured hipGraph */
   FFTB_PLAN_HOST_ONLY = 8,   /* build and validate the host tables only; no device work (testing) */
-  FFTB_PLAN_MFMA = 16        /* FFTB_C64 only: radix-16 stages as FP32 MFMA dense products */
+  FFTB_PLAN_MFMA = 16        /* FFTB_C64 only: radix-16 stages as FP32 MFMA dense products (the
+                                inverse fold's length-16 transforms of band-inner plans with y
+                                classes of 16, the in-lane DFT_16 of 128-point register lines);
+                                UNSUPPORTED for a plan with neither */
 };
 
 typedef struct fftb_plan_s* fftb_plan; /* opaque */
