@@ -427,11 +427,12 @@ __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S, const TwEntry<T>*
     __syncthreads();
     // NBF blocks per round trip (their loads are all issued before the first
     // is accumulated; two measured best: four cost registers and time; one
-    // for blocks of 32, for class pairs and for complex64 band-inner folds,
-    // whose accumulators fill the registers)
-    constexpr int NBF = FFTB_FOLD_BLOCKS > 0
-                            ? FFTB_FOLD_BLOCKS
-                            : ((M > 16 || PAIR || (BL && std::is_same<T, float>::value)) ? 1 : 2);
+    // for blocks of 32, for complex128 class pairs, for complex64 band-inner
+    // folds of two bands per lane and for the matrix-core fold, whose
+    // accumulators fill the registers)
+    constexpr int NBF = FFTB_FOLD_BLOCKS > 0 ? FFTB_FOLD_BLOCKS
+                        : (PAIR && std::is_same<T, float>::value && !MF) ? 2
+                        : ((M > 16 || PAIR || (BL && std::is_same<T, float>::value)) ? 1 : 2);
     static_assert(NBF >= 1, "fold blocks per round trip");
     // the plane's column scratch as a buffer (the host keeps it below 2 GiB):
     // a block's M loads share one offset register
