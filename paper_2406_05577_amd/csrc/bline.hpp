@@ -71,6 +71,21 @@ __device__ __forceinline__ void bl_fence(cpx<T>* v, int k0, int k1) {
   for (int k = k0; k < k1; ++k) asm volatile("" : "+v"(v[k].re), "+v"(v[k].im)::"memory");
 }
 
+// Values per group of twiddle reads and partner fetches (two measured no
+// better than four for the longest complex128 lines).
+template <int E, typename T>
+constexpr int bl_group() {
+  return 4;
+}
+// The DPP round grouped too: only for long complex128 lines, where the
+// partner copies of a whole line overflowed the registers (the 45 x 4 z lines
+// of 180: 126-186 extra registers without it, 2.12 -> 2.02 ms per column
+// kernel at 144x160x180; shorter lines measured better ungrouped)
+template <int E, typename T>
+constexpr bool bl_group_dpp() {
+  return sizeof(T) == 8 && E >= 32;
+}
+
 template <int E, int H, int S, typename T, int BW = band_width<T>()>
 struct BLineCtx {
   static constexpr int kBW = BW;  // bands per row of lanes
@@ -108,6 +123,7 @@ template <int HS, int I, int E, int H, int S, typename T, int BW>
 __device__ __forceinline__ void bl_rounds(cpx<T>* v, const BLineCtx<E, H, S, T, BW>& c) {
   if constexpr (HS >= 1) {
     constexpr int D = HS * BW;
+    constexpr int G = bl_group<E, T>();
     const T sg = c.sgn[I];
     if constexpr (D <= 8) {
       // partners 4 or 8 lanes apart sit in the same row of 16: DPP moves
@@ -116,15 +132,17 @@ __device__ __forceinline__ void bl_rounds(cpx<T>* v, const BLineCtx<E, H, S, T, 
       for (int k = 0; k < E; ++k) {
         const T pr = dpp_xor<D>(v[k].re), pi = dpp_xor<D>(v[k].im);
         v[k] = {ffma(sg, v[k].re, pr), ffma(sg, v[k].im, pi)};
+        if constexpr (bl_group_dpp<E, T>())
+          if (k % G == G - 1 && k + 1 < E) bl_fence(v, k - G + 1, k + 1 + G < E ? k + 1 + G : E);
       }
     } else {
       const int src = ((threadIdx.x & 63) ^ D) << 2;
-      // in groups of four values, so that the fetched values do not all stay live
+      // in groups of G values, so that the fetched values do not all stay live
 #pragma unroll
       for (int k = 0; k < E; ++k) {
         const T pr = lane_read(src, v[k].re), pi = lane_read(src, v[k].im);
         v[k] = {ffma(sg, v[k].re, pr), ffma(sg, v[k].im, pi)};
-        if ((k & 3) == 3 && k + 1 < E) bl_fence(v, k - 3, k + 5 < E ? k + 5 : E);
+        if (k % G == G - 1 && k + 1 < E) bl_fence(v, k - G + 1, k + 1 + G < E ? k + 1 + G : E);
       }
     }
     if constexpr (HS == 2) {
@@ -152,8 +170,9 @@ template <int E, int H, int S, typename T, int BW>
 __device__ __forceinline__ void bline_fft(cpx<T>* v, const BLineCtx<E, H, S, T, BW>& c) {
   dft<E, S>(v);
   if constexpr (H > 1) {
-    // in groups of four: the scheduler would otherwise issue every table read
-    // at once and keep all E-1 twiddles live beside the line
+    // in groups of G: the scheduler would otherwise issue every table read at
+    // once and keep all E-1 twiddles live beside the line
+    constexpr int G = bl_group<E, T>();
 #pragma unroll
     for (int k = 1; k < E; ++k) {
       const TwEntry<T> w = c.tw[k];
@@ -161,7 +180,7 @@ __device__ __forceinline__ void bline_fft(cpx<T>* v, const BLineCtx<E, H, S, T, 
         v[k] = cmul_hl(v[k], cpx<float>{w.re, w.im}, cpx<float>{w.lre, w.lim});
       else
         v[k] = cmul(v[k], cpx<double>{w.re, w.im});
-      if ((k & 3) == 3 && k + 1 < E) bl_fence(v, k - 3, k + 1);
+      if (k % G == G - 1 && k + 1 < E) bl_fence(v, k - G + 1, k + 1);
     }
     bl_rounds<H / 2, 0, E, H, S, T, BW>(v, c);
   }
