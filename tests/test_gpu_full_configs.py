@@ -25,6 +25,10 @@ CONFIGS = [
     ("c4", "c128", 0),
     ("c5", "c128", 0),
     ("x1", "c128", 0),   # the paper's experiment shape
+    # the precision form with its radix-16 stages on the matrix cores (16):
+    # the inverse fold's length-16 transforms on the y axes of 96 and 160
+    ("c4", "c64", 5 | 16),
+    ("c5", "c64", 5 | 16),
 ]
 
 
