@@ -68,7 +68,7 @@ def test_column_tables_match_map(dims, semi, k):
     assert p.info["sphere_elems"] == lin.shape[0] * 2
 
 
-def test_survey_shapes():
+def test_128cube_sphere_columns_and_slabs():
     # occupied columns and slabs of the 128^3 |G|<=32 sphere
     w = synth.make_workload("c2", nbands=1)
     p = host_plan(w.dims, [w.spheres[0].lin], nb=256)
