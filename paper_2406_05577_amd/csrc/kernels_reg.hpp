@@ -473,14 +473,19 @@ __device__ void k2r_inv_task(const KArgs& a, int t, cpx<T>* S, const TwEntry<T>*
         if constexpr (std::is_same<T, float>::value) {
           cpx<T> wl = troot[2 * tb + 1];
           if (!use) wl = cpx<T>{0, 0};
-#pragma unroll
-          for (int f = 0; f < FB; ++f)
-#pragma unroll
-            for (int k = 0; k < M; ++k) u[f][k] = cmac_hl(u[f][k], v[f][k], w, wl);
           if constexpr (PAIR) {
-            const cpx<T> w2{sg * w.re, sg * w.im}, wl2{sg * wl.re, sg * wl.im};
+            // one compensated product serves both classes (r2's root is +-r's)
 #pragma unroll
-            for (int k = 0; k < M; ++k) u2[k] = cmac_hl(u2[k], v[0][k], w2, wl2);
+            for (int k = 0; k < M; ++k) {
+              const cpx<T> p = cmul_hl(v[0][k], w, wl);
+              u[0][k] = cadd(u[0][k], p);
+              u2[k] = {ffma(sg, p.re, u2[k].re), ffma(sg, p.im, u2[k].im)};
+            }
+          } else {
+#pragma unroll
+            for (int f = 0; f < FB; ++f)
+#pragma unroll
+              for (int k = 0; k < M; ++k) u[f][k] = cmac_hl(u[f][k], v[f][k], w, wl);
           }
         } else {
 #pragma unroll
