@@ -178,6 +178,63 @@ def summarize_counters(args):
         json.dump(d, f, indent=1, sort_keys=True)
 
 
+def summarize_pmc(dirs):
+    """Per-kernel means of the counters in rocprofv3 --pmc passes (one folder
+    per pass), with the ratios read from them: instructions per wave, the
+    share of resident wave time spent waiting or issuing VALU / LDS work, LDS
+    bank-conflict cycles per LDS-active cycle, the L2 hit rate and the mean
+    latency of L1-to-L2 reads. With GRBM_GUI_ACTIVE (busy cycles summed over
+    the 8 XCDs) it also gives the engine clock during the dispatch and the
+    mean resident waves per CU (SQ_WAVE_CYCLES counts in units of 4 cycles,
+    over the 256 CUs). Prints markdown tables."""
+    acc = {}
+    dur = {}
+    for d in dirs:
+        for r in _counter_rows(d):
+            key = kernel_id(r["Kernel_Name"])
+            if key is None:
+                continue
+            acc.setdefault(key, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+            dur.setdefault(key, {})[(d, r["Dispatch_Id"])] = (
+                int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    mean = {k: {c: sum(v) / len(v) for c, v in cs.items()} for k, cs in acc.items()}
+    names = sorted({c for cs in mean.values() for c in cs})
+    print("| kernel | " + " | ".join(names) + " |")
+    print("|---|" + "---|" * len(names))
+    for k in sorted(mean):
+        print(f"| {k} | " + " | ".join(f"{mean[k][c]:.4g}" if c in mean[k] else "" for c in names) + " |")
+
+    def ratio(m, a, b):
+        return m[a] / m[b] if a in m and b in m and m[b] else None
+
+    cols = [("VALU insts / wave", "SQ_INSTS_VALU", "SQ_WAVES"),
+            ("LDS insts / wave", "SQ_INSTS_LDS", "SQ_WAVES"),
+            ("VMEM reads / wave", "SQ_INSTS_VMEM_RD", "SQ_WAVES"),
+            ("VMEM writes / wave", "SQ_INSTS_VMEM_WR", "SQ_WAVES"),
+            ("waiting / resident", "SQ_WAIT_INST_ANY", "SQ_WAVE_CYCLES"),
+            ("VALU issuing / resident", "SQ_ACTIVE_INST_VALU", "SQ_WAVE_CYCLES"),
+            ("LDS issuing / resident", "SQ_ACTIVE_INST_LDS", "SQ_WAVE_CYCLES"),
+            ("bank-conflict cycles / LDS-active cycle", "SQ_LDS_BANK_CONFLICT", "SQ_ACTIVE_INST_LDS")]
+    print()
+    extra = ["L2 hit rate", "L2 read latency (cycles)", "clock (GHz)", "resident waves / CU"]
+    print("| kernel | mean dispatch ms | " + " | ".join(c[0] for c in cols + [(e,) for e in extra]) + " |")
+    print("|---|---|" + "---|" * (len(cols) + len(extra)))
+    for k in sorted(mean):
+        m = mean[k]
+        ms = sum(dur[k].values()) / len(dur[k]) / 1e6
+        cells = [ratio(m, a, b) for _, a, b in cols]
+        hit = lat = ghz = waves = None
+        if "TCC_HIT_sum" in m and "TCC_MISS_sum" in m:
+            hit = m["TCC_HIT_sum"] / max(m["TCC_HIT_sum"] + m["TCC_MISS_sum"], 1.0)
+        lat = ratio(m, "TCP_TCC_READ_REQ_LATENCY_sum", "TCP_TCC_READ_REQ_sum")
+        if m.get("GRBM_GUI_ACTIVE"):
+            ghz = m["GRBM_GUI_ACTIVE"] / 8.0 / (ms * 1e6)
+            if "SQ_WAVE_CYCLES" in m:
+                waves = 4.0 * m["SQ_WAVE_CYCLES"] / (m["GRBM_GUI_ACTIVE"] / 8.0 * 256.0)
+        cells += [hit, lat, ghz, waves]
+        print(f"| {k} | {ms:.3f} | " + " | ".join("" if c is None else f"{c:.3g}" for c in cells) + " |")
+
+
 def host_description():
     """nproc, CPU model and the BLAS thread count of the host."""
     model = platform.processor() or ""
@@ -438,10 +495,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--summarize-counters", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="rocprofv3 --pmc output folders: write profiles/traffic.json for --workload")
+    ap.add_argument("--summarize-pmc", nargs="+", metavar="DIR",
+                    help="rocprofv3 --pmc output folders: print per-kernel counter means and ratios")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 1 GiB device-to-device copy three times (the reference "
                          "kernel whose FETCH_SIZE / WRITE_SIZE calibrate the HBM counters)")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(args.summarize_pmc)
+        return
     if args.summarize_counters:
         summarize_counters(args)
         return
