@@ -346,7 +346,7 @@ size_t plane_lds_bil(const fftb_plan_s& P, int n1, int bw, int e2, int h2, bool 
   tw_at = static_cast<int>(b);
   // the twiddle table (lines of more than one position), then the slab-line
   // offsets of the nx x positions
-  return b + (h2 > 1 ? static_cast<size_t>(e2) * h2 * 16 : 0) + static_cast<size_t>(P.nx) * 4;
+  return b + (h2 > 1 ? static_cast<size_t>(tw_row_stride(e2)) * h2 * 16 : 0) + static_cast<size_t>(P.nx) * 4;
 }
 
 // Cut a sphere's slabs into Q contiguous ranges with about equal column counts.

@@ -38,9 +38,9 @@ struct alignas(16) TwEntry<float> {
   float re, im, lre, lim;
 };
 
-// Fill tab[h*E + k] = w_N^{S*h*k} (N = E*H) from the forward-sign root table
-// of length N (FP32: hi and lo tables). Block-cooperative; the caller
-// synchronises before use.
+// Fill tab[h*R + k] = w_N^{S*h*k} (N = E*H, R = tw_row_stride(E)) from the
+// forward-sign root table of length N (FP32: hi and lo tables).
+// Block-cooperative; the caller synchronises before use.
 template <int S, typename T>
 __device__ void bl_fill_twiddles(TwEntry<T>* tab, const cpx<T>* __restrict__ root,
                                  const cpx<T>* __restrict__ root_lo, int E, int H) {
@@ -56,7 +56,7 @@ __device__ void bl_fill_twiddles(TwEntry<T>* tab, const cpx<T>* __restrict__ roo
       e.lre = l.re;
       e.lim = sg * l.im;
     }
-    tab[i] = e;
+    tab[h * tw_row_stride(E) + k] = e;
   }
 }
 
@@ -99,7 +99,7 @@ struct BLineCtx {
 template <int E, int H, int S, typename T, int BW = band_width<T>()>
 __device__ __forceinline__ BLineCtx<E, H, S, T, BW> bline_ctx(int h, const TwEntry<T>* tab) {
   BLineCtx<E, H, S, T, BW> c;
-  c.tw = tab + h * E;
+  c.tw = tab + h * tw_row_stride(E);
   if constexpr (H > 1) {
     int i = 0;
 #pragma unroll

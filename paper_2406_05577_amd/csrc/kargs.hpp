@@ -12,6 +12,13 @@ constexpr int kAxisStages = 8;
 template <typename T>
 constexpr int kPairRegLines = sizeof(T) == 4 ? 2 : 1;
 
+// Row stride, in 16-byte entries, of the band-inner lines' LDS twiddle table
+// (one row of E twiddles per line position): odd, so that the rows a wave
+// reads at once start in different LDS banks (rows of 16 entries, 256 bytes,
+// all began in the same banks). The kernels and the host's LDS sizing both
+// use it.
+constexpr int tw_row_stride(int e) { return e | 1; }
+
 struct AxisDev {
   int n;
   int nst;

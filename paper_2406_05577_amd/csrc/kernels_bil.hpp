@@ -135,7 +135,7 @@ __global__ void __launch_bounds__(256) k1b_kernel(const KArgs a) {
 
 template <int S, typename T, int E, int H>
 hipError_t bil_launch_k1(const KArgs& a, int grid, int threads, hipStream_t st) {
-  const size_t lds = static_cast<size_t>(E) * H * sizeof(TwEntry<T>);
+  const size_t lds = static_cast<size_t>(tw_row_stride(E)) * H * sizeof(TwEntry<T>);
   hipLaunchKernelGGL((k1b_kernel<S, T, E, H>), dim3(grid), dim3(threads), lds, st, a);
   return hipGetLastError();
 }

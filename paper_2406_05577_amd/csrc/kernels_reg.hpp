@@ -1158,7 +1158,7 @@ __global__ void __launch_bounds__(512) k2r_kernel(const KArgs a) {
   // band-inner lines: the x twiddles w_nx^{h*k} staged in LDS once per block,
   // followed by the per-task table of slab-line offsets of the x positions
   TwEntry<T>* tab = reinterpret_cast<TwEntry<T>*>(smem_raw + a.lds_twx);
-  int* xo = reinterpret_cast<int*>(smem_raw + a.lds_twx + (H > 1 ? E * H : 0) * sizeof(TwEntry<T>));
+  int* xo = reinterpret_cast<int*>(smem_raw + a.lds_twx + (H > 1 ? tw_row_stride(E) * H : 0) * sizeof(TwEntry<T>));
   if constexpr (BL) {
     if constexpr (H > 1)
       bl_fill_twiddles<S, T>(tab, reinterpret_cast<const cpx<T>*>(a.rootx),
