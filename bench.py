@@ -298,10 +298,12 @@ class Form:
             fl = flags
         if autotune:
             fl |= 2
-        if tuning is None:
+        self.full = name.endswith("_full")
+        if tuning is None and not self.full:
+            # (the padded-cube comparator's map occupies every slab: its plans
+            # take the defaults)
             tuning = tuning_for(recipe, dtype, fl)
         self.recipe, self.dtype, self.flags, self.tuning_req = recipe, dtype, fl, tuning
-        self.full = name.endswith("_full")
         tdt = torch.complex128 if dtype == "c128" else torch.complex64
         self.es = 16 if dtype == "c128" else 8
         t0 = time.perf_counter()
