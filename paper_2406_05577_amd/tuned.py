@@ -17,11 +17,13 @@ def _both(inv: dict, fwd: dict) -> dict:
     return out
 
 
-# The autotuner's picks where they differ from the defaults: the forward plane
-# kernel with half the classes (classes of 16) and 512 threads, one workgroup
-# per CU (forward plane kernel 11.10 -> 11.02 ms at 144x160x180 and 2.85 ->
-# 2.79 ms at 128^3, complex128). Every other benchmark workload's pick is its
-# default tiling.
+# The autotuner's picks where they differ from the defaults. 144x160x180 and
+# 128^3, complex128: the forward plane kernel with half the classes (classes
+# of 16) and 512 threads, one workgroup per CU (11.10 -> 11.02 ms and 2.85 ->
+# 2.79 ms). 256^3 (register lines): the inverse with 16 classes of 16 (a
+# smaller band chunk in complex128, smaller column tiles in complex64): 8.58
+# -> 8.76 and 13.04 -> 13.67 round trips/s. Every other benchmark workload's
+# pick is its default tiling.
 TUNED = {
     ("c5", "c128", 0): _both(
         dict(band_chunk=8, y_classes=10, x_rows=1, col_tile=16, threads=512, path=3, acc=2),
@@ -29,6 +31,12 @@ TUNED = {
     ("c2", "c128", 0): _both(
         dict(band_chunk=8, y_classes=8, x_rows=1, col_tile=8, threads=512, path=3, acc=2),
         dict(band_chunk=8, y_classes=8, x_rows=1, col_tile=8, threads=512, path=3, acc=3)),
+    ("x1", "c128", 0): _both(
+        dict(band_chunk=4, y_classes=16, x_rows=1, col_tile=8, threads=512, path=2, acc=0, lanes=16),
+        dict(band_chunk=4, y_classes=16, x_rows=1, col_tile=8, threads=512, path=2, acc=3, lanes=16)),
+    ("x1", "c64", 0): _both(
+        dict(band_chunk=8, y_classes=16, x_rows=1, col_tile=4, threads=512, path=2, acc=0, lanes=16),
+        dict(band_chunk=8, y_classes=16, x_rows=1, col_tile=4, threads=512, path=2, acc=3, lanes=16)),
 }
 
 

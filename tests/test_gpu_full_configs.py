@@ -29,6 +29,7 @@ CONFIGS = [
     # the inverse fold's length-16 transforms on the y axes of 96 and 160
     ("c4", "c64", 5 | 16),
     ("c5", "c64", 5 | 16),
+    ("x1", "c64", 0),    # the 256^3 shape in complex64 (its own frozen tiling)
 ]
 
 
